@@ -1,0 +1,112 @@
+"""Invariant checks and canonical forms for 1-skeletons (test helpers).
+
+A complex is given as coordinates X [V, D] (float64), sign-vectors S [V, M]
+(int8 in {+1, 0, -1}) and edges [E, 2]. Nothing here imports the oracle or the
+GPU library.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from brute import entry_values, join
+
+
+def unpack_signs(packed: np.ndarray, M: int) -> np.ndarray:
+    """2-bit packed rows ([V, Wd] uint64; entry i at word i>>5, bits 2(i&31);
+    code 00 = 0, 01 = +, 10 = -) to int8 sign-vectors [V, M]."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint64)
+    V, Wd = packed.shape
+    idx = np.arange(M)
+    words = packed[:, idx >> 5]
+    codes = (words >> (2 * (idx & 31)).astype(np.uint64)) & np.uint64(3)
+    out = np.zeros((V, M), np.int8)
+    out[codes == 1] = 1
+    out[codes == 2] = -1
+    if np.any(codes == 3):
+        raise AssertionError("invalid sign code 11")
+    return out
+
+
+def canonical(X, S, edges):
+    """Vertices sorted by sign-vector bytes; edges as sorted (min, max) pairs
+    of canonical ids. Returns (X, S, edges, perm) with perm[old] = new."""
+    S = np.ascontiguousarray(S, dtype=np.int8)
+    keys = S.view(np.dtype((np.void, S.shape[1]))).ravel()
+    order = np.argsort(keys, kind="stable")
+    perm = np.empty(len(order), np.int64)
+    perm[order] = np.arange(len(order))
+    E = perm[np.asarray(edges, np.int64)]
+    E = np.sort(E, axis=1)
+    E = E[np.lexsort((E[:, 1], E[:, 0]))] if len(E) else E.reshape(0, 2)
+    return X[order], S[order], E, perm
+
+
+def assert_same_complex(A, B, coord_tol=1e-10):
+    """Bit-exact sign-vectors, counts and canonical incidence; coordinates to tol."""
+    XA, SA, EA, _ = canonical(*A)
+    XB, SB, EB, _ = canonical(*B)
+    assert SA.shape == SB.shape, f"vertex/entry counts differ: {SA.shape} vs {SB.shape}"
+    assert np.array_equal(SA, SB), "sign-vectors differ"
+    assert EA.shape == EB.shape, f"edge counts differ: {EA.shape} vs {EB.shape}"
+    assert np.array_equal(EA, EB), "edge incidence differs"
+    err = np.max(np.abs(XA - XB)) if len(XA) else 0.0
+    assert err <= coord_tol, f"coordinates differ by {err}"
+
+
+def check_invariants(net, lo, hi, X, S, edges, include_output=False, zero_tol=1e-9, full=True):
+    """Properties that hold for the 1-skeleton of any generic instance."""
+    V, M = S.shape
+    D = X.shape[1]
+    edges = np.asarray(edges, np.int64)
+    # a vertex is a 0-cell: exactly D zeros (Sec. 4.1)
+    zc = (S == 0).sum(1)
+    assert np.all(zc == D), f"vertices with != D zeros: {np.nonzero(zc != D)[0][:5]}"
+    # interior cells are + on the domain entries; no vertex outside the box
+    assert np.all(S[:, :2 * D] >= 0), "negative box entry"
+    for j in range(D):
+        at_lo = S[:, 2 * j] == 0
+        at_hi = S[:, 2 * j + 1] == 0
+        assert np.all(X[at_lo, j] == lo[j]) and np.all(X[at_hi, j] == hi[j]), "box coordinate not exact"
+        inner = ~(at_lo | at_hi)
+        assert np.all((X[inner, j] > lo[j]) & (X[inner, j] < hi[j])), "vertex outside the box"
+    # distinct cells have distinct sign-vectors
+    keys = np.ascontiguousarray(S).view(np.dtype((np.void, M))).ravel()
+    assert len(np.unique(keys)) == V, "duplicate sign-vectors"
+    # edges: D-1 shared zeros, no +/- conflict (Sec. 4.1, 4.2.2)
+    a, b = edges[:, 0], edges[:, 1]
+    assert np.all(a != b)
+    shared = ((S[a] == 0) & (S[b] == 0)).sum(1)
+    assert np.all(shared == D - 1), "edge without D-1 shared zeros"
+    conflict = (S[a] != 0) & (S[b] != 0) & (S[a] != S[b])
+    assert not conflict.any(), "edge endpoints in conflict"
+    ek = np.sort(edges, axis=1)
+    assert len(np.unique(ek, axis=0)) == len(ek), "duplicate edges"
+    # vertex degree = 2D - (number of zero box entries), Sec. 4.1 at k = 0
+    zbox = (S[:, :2 * D] == 0).sum(1)
+    deg = np.bincount(edges.ravel(), minlength=V)
+    assert np.array_equal(deg, 2 * D - zbox), "degree != 2D - z_box"
+    assert 2 * len(edges) == np.sum(2 * D - zbox)
+    if not full:
+        return
+    # validation of Sec. 5.1.1: zero entries evaluate to ~0, signs agree elsewhere
+    vals = entry_values(net, lo, hi, X, include_output)
+    assert np.all(np.abs(vals[S == 0]) < zero_tol), f"max |z| at zeros {np.abs(vals[S == 0]).max()}"
+    nz = S != 0
+    assert np.all(np.sign(vals[nz]) == S[nz]), "forward-pass sign differs from sign-vector"
+    # midpoint of each edge lies in the edge's cell: sign = join
+    jn = np.where(S[a] == 0, S[b], S[a])
+    mid = 0.5 * (X[a] + X[b])
+    mv = entry_values(net, lo, hi, mid, include_output)
+    assert np.all(np.abs(mv[jn == 0]) < 1e-7), "edge leaves a hyperplane it should lie on"
+    assert np.all(np.sign(mv[jn != 0]) == jn[jn != 0]), "edge midpoint outside its cell"
+
+
+def digest(S, edges):
+    """sha256 over the canonical sign-vectors and canonical edge list."""
+    import hashlib
+    X = np.zeros((len(S), 1))
+    _, Sc, Ec, _ = canonical(X, S, edges)
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(Sc, np.int8).tobytes())
+    h.update(np.ascontiguousarray(Ec, np.int64).tobytes())
+    return h.hexdigest()

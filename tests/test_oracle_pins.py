@@ -1,0 +1,208 @@
+"""Pins for the CPU oracle, independent of it: brute force, closed forms,
+Euler characteristic, invariants, and planted mistakes that must be caught.
+
+The paper prints no worked numbers (its figures are not recoverable), so every
+pin here comes from the definitions: a vertex is a point of the box with
+exactly D zero entries in its sign-vector (Sec. 3.3, 4.1), an edge joins two
+vertices sharing D-1 zeros whose midpoint carries their join (Sec. 3.5).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import brute
+from checks import assert_same_complex, canonical, check_invariants
+from paper_2306_07212_amd import workloads as wl
+
+
+def _oracle_complex(oracle_lib, net, box, include_output=False, mutation=0):
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=include_output, mutation=mutation)
+    return r, (r.X, r.S, r.edges)
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("widths,seed", [([2, 6, 1], 11), ([2, 9, 1], 12), ([3, 5, 1], 13), ([3, 7, 1], 14),
+                                         ([1, 7, 1], 15)])
+def test_single_layer_matches_arrangement(oracle_lib, widths, seed):
+    """One hidden layer = an affine hyperplane arrangement on the box: every
+    D-subset of hyperplanes and box faces solved, edges along each line."""
+    net = wl.he_mlp(widths, seed)
+    box = wl.cube(widths[0])
+    r, got = _oracle_complex(oracle_lib, net, box)
+    X, S = brute.vertices(net, box.lo, box.hi)
+    E = brute.arrangement_edges(X, S)
+    assert_same_complex(got, (X, S, E))
+    check_invariants(net, box.lo, box.hi, *got)
+
+
+@pytest.mark.parametrize("widths,seed,incl", [([2, 4, 4, 1], 21, False), ([2, 3, 3, 3, 1], 22, False),
+                                              ([3, 4, 4, 1], 23, False), ([2, 4, 4, 1], 24, True),
+                                              ([1, 4, 4, 4, 1], 25, False), ([2, 5, 3, 1], 26, True)])
+def test_multilayer_matches_bruteforce(oracle_lib, widths, seed, incl):
+    """Folded hyperplanes: every D-subset of entries under every activation
+    pattern below it, confirmed by the forward pass; edges by the midpoint test."""
+    net = wl.he_mlp(widths, seed)
+    box = wl.cube(widths[0])
+    r, got = _oracle_complex(oracle_lib, net, box, include_output=incl)
+    X, S = brute.vertices(net, box.lo, box.hi, include_output=incl)
+    E = brute.edges_by_midpoint(net, box.lo, box.hi, X, S, include_output=incl)
+    assert_same_complex(got, (X, S, E))
+    check_invariants(net, box.lo, box.hi, *got, include_output=incl)
+
+
+def test_d1_closed_form(oracle_lib):
+    """D = 1, one hidden layer: vertices are the box ends and the roots
+    -b_i / w_i inside the box; edges join consecutive points."""
+    net = wl.he_mlp([1, 12, 1], 31)
+    box = wl.cube(1)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    roots = -net.b[0] / net.W[0][:, 0]
+    pts = np.sort(np.concatenate([[box.lo[0], box.hi[0]], roots[(roots > -1) & (roots < 1)]]))
+    got = np.sort(r.X[:, 0])
+    assert len(got) == len(pts) and np.max(np.abs(got - pts)) < 1e-14
+    assert r.E == r.V - 1
+    assert r.V == 2 + r.steps[:, 2].sum()
+    order = np.argsort(r.X[:, 0])
+    rank = np.empty_like(order)
+    rank[order] = np.arange(len(order))
+    e = np.sort(rank[r.edges], axis=1)
+    assert np.all(e[:, 1] - e[:, 0] == 1)
+
+
+def test_affine_reduction(oracle_lib):
+    """A first layer that is positive on the whole box makes the network affine
+    there, so the second layer is a plain hyperplane arrangement of the composed
+    maps W2 W1, W2 b1 + b2 (and the first layer splits nothing)."""
+    net = wl.he_mlp([2, 4, 6, 1], 41)
+    net.b[0] = np.abs(net.b[0]) + 50.0
+    box = wl.cube(2)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    assert r.steps[:4, 2].sum() == 0
+    comp = wl.Net([2, 6, 1], [net.W[1] @ net.W[0], net.W[2]], [net.W[1] @ net.b[0] + net.b[1], net.b[2]])
+    r2 = oracle_lib.extract(comp, box.lo, box.hi)
+    # drop the first-layer entries (all +) and compare
+    S = np.delete(r.S, np.arange(4, 8), axis=1)
+    assert np.all(r.S[:, 4:8] == 1)
+    assert_same_complex((r.X, S, r.edges), (r2.X, r2.S, r2.edges), coord_tol=1e-12)
+    X, Sb = brute.vertices(comp, box.lo, box.hi)
+    assert_same_complex((r2.X, r2.S, r2.edges), (X, Sb, brute.arrangement_edges(X, Sb)))
+
+
+# ------------------------------------------------------------ Euler, regions
+
+@pytest.mark.parametrize("maker", [wl.plain_small, lambda: wl.he_mlp([2, 16, 16, 1], 51),
+                                   lambda: wl.he_mlp([2, 10, 10, 10, 1], 52)])
+def test_euler_2d(oracle_lib, maker):
+    """D = 2: V - E + F = 1 with F counted by tracing faces of the plane graph,
+    and equal to the number of regions found by perturbation (Sec. 4.1)."""
+    net = maker()
+    box = wl.cube(2)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    faces = brute.planar_face_count(r.X, r.edges) - 1
+    assert r.V - r.E + faces == 1
+    regs = brute.regions_by_perturbation(r.S, r.edges, 2)
+    assert len(regs) == faces
+    # every sampled point falls in one of those regions
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(-1, 1, (20000, 2))
+    s = brute.sign_vector(brute.entry_values(net, box.lo, box.hi, pts), tol=0.0)
+    assert {row.tobytes() for row in s} <= regs
+
+
+def test_region_coverage_3d(oracle_lib):
+    """D = 3: every sampled point's sign-vector is a region obtained by
+    perturbing both zeros of some edge."""
+    net = wl.he_mlp([3, 6, 6, 1], 61)
+    box = wl.cube(3)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    regs = brute.regions_by_perturbation(r.S, r.edges, 3)
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(-1, 1, (20000, 3))
+    s = brute.sign_vector(brute.entry_values(net, box.lo, box.hi, pts), tol=0.0)
+    hit = {row.tobytes() for row in s}
+    assert hit <= regs
+    assert len(hit) > 0.5 * len(regs)
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("maker,incl", [(wl.plain_small, False), (wl.differentiable_small, True),
+                                        (lambda: wl.he_mlp([4, 6, 6, 1], 71), False)])
+def test_invariants(oracle_lib, maker, incl):
+    net = maker()
+    box = wl.cube(net.D)
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=incl)
+    check_invariants(net, box.lo, box.hi, r.X, r.S, r.edges, include_output=incl)
+    assert r.min_margin > 1e-12
+
+
+@pytest.mark.slow
+def test_invariants_differentiable_workload(oracle_lib):
+    net = wl.differentiable()
+    box = wl.cube(3)
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=True)
+    check_invariants(net, box.lo, box.hi, r.X, r.S, r.edges, include_output=True)
+    assert r.min_margin > 1e-12
+
+
+def test_vertex_solve_reproduces_vertices(oracle_lib):
+    """The per-vertex solve (used for sampled checks at full size) agrees with
+    brute force and with subdivision."""
+    for widths, seed, incl in [([2, 8, 8, 1], 1, False), ([3, 4, 4, 1], 23, False), ([2, 5, 3, 1], 26, True)]:
+        net = wl.he_mlp(widths, seed)
+        box = wl.cube(widths[0])
+        r = oracle_lib.extract(net, box.lo, box.hi, include_output=incl)
+        x = oracle_lib.vertex_solve(net, box.lo, box.hi, r.S, include_output=incl)
+        assert np.max(np.abs(x - r.X)) < 1e-12
+        Xb, Sb = brute.vertices(net, box.lo, box.hi, include_output=incl)
+        xb = oracle_lib.vertex_solve(net, box.lo, box.hi, Sb, include_output=incl)
+        assert np.max(np.abs(xb - Xb)) < 1e-12
+
+
+def test_forward_matches_numpy(oracle_lib):
+    net = wl.he_mlp([3, 7, 5, 2], 81)
+    x = np.random.default_rng(2).uniform(-1, 1, (50, 3))
+    a = oracle_lib.forward(net, x)
+    b = brute.forward_all(net, x)
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_step_counts_consistent(oracle_lib):
+    """V grows by the splits; E by the splits plus one edge per 2-face pair
+    (K_n / 2); K_n = sum over splits of z_box + 2 (D - 1 - z_box)."""
+    net = wl.he_mlp([3, 6, 6, 1], 91)
+    box = wl.cube(3)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    st = r.steps
+    for n in range(len(st) - 1):
+        V, E, S, K = st[n]
+        assert st[n + 1, 0] == V + S
+        assert st[n + 1, 1] == E + S + K // 2
+        assert K % 2 == 0
+    V, E, S, K = st[-1]
+    assert r.V == V + S and r.E == E + S + K // 2
+
+
+# --------------------------------------------------------- planted mistakes
+
+def _pins_pass(oracle_lib, net, box, mutation, incl=False):
+    try:
+        r, got = _oracle_complex(oracle_lib, net, box, include_output=incl, mutation=mutation)
+        X, S = brute.vertices(net, box.lo, box.hi, include_output=incl)
+        E = brute.edges_by_midpoint(net, box.lo, box.hi, X, S, include_output=incl)
+        assert_same_complex(got, (X, S, E))
+        check_invariants(net, box.lo, box.hi, *got, include_output=incl)
+        if net.D == 2:
+            assert r.V - r.E + brute.planar_face_count(r.X, r.edges) - 1 == 1
+    except (AssertionError, oracle_lib.OracleError, IndexError, ValueError):
+        return False
+    return True
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5])
+def test_planted_mistakes_are_caught(oracle_lib, mutation):
+    cases = [(wl.he_mlp([2, 4, 4, 1], 24), wl.cube(2)), (wl.he_mlp([3, 4, 4, 1], 23), wl.cube(3))]
+    assert all(_pins_pass(oracle_lib, n, b, 0) for n, b in cases)
+    assert not all(_pins_pass(oracle_lib, n, b, mutation) for n, b in cases)
