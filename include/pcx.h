@@ -1,0 +1,127 @@
+/*
+ * pcx.h -- C ABI of the MI355X (gfx950) edge-subdivision library libpcx.so.
+ *
+ * Polyhedral complex extraction from ReLU networks by edge subdivision
+ * (Berzins, ICML 2023). A continuous piecewise-affine ReLU MLP (Sec. 3.4:
+ * x^(l) = ReLU(W^(l) x^(l-1) + b^(l))) and an input box in R^D go in; the
+ * 1-skeleton of the polyhedral complex its folded hyperplanes induce on the
+ * box comes out: vertex coordinates, packed sign-vectors (Sec. 3.3) and an edge
+ * list. Every neuron of every hidden layer is processed in layer order with
+ * the five steps of Sec. 4.2 (evaluate, sign, find splitting edges,
+ * interpolate and split, connect new vertices sharing a 2-face).
+ *
+ * Conventions shared by every call
+ *  - All floating point is IEEE binary64.
+ *  - W^(l) is row-major [N_l][N_{l-1}] (z = W x + b); b^(l) is [N_l].
+ *  - widths = {D, N_1, ..., N_{L-1}, N_L}; layers 1..L-1 are hidden (ReLU),
+ *    layer L is the output. Hidden neurons are always subdivided; output
+ *    neurons only with pcx_opts.include_output (their zero level set).
+ *  - Sign-vector entries (Sec. 4.1): the 2D box half-spaces first, entry 2j
+ *    is x_j - lo_j >= 0 and entry 2j+1 is hi_j - x_j >= 0 (interior cells are
+ *    + there), then the subdivided neurons layer by layer in index order.
+ *  - Sign-vector packing: 2 bits per entry, code 00 = 0, 01 = +, 10 = -
+ *    (11 never occurs), so the join of two cells (Sec. 3.5) is a bitwise OR.
+ *    A row is Wd uint64 words. Word 0 holds the box entries (entry e at bits
+ *    2e, so D <= 16). Each subdivided layer starts on a fresh word: neuron i
+ *    of subdivided layer l sits in word lw_l + (i >> 5), bits 2(i & 31),
+ *    where lw_1 = 1 and lw_{l+1} = lw_l + ceil(N_l / 32). Unused bits are 0.
+ *  - Errors: every int-returning call returns PCX_OK (0) or a negative code;
+ *    pcx_last_error() gives a message for the calling thread. Inputs are
+ *    copied during the call; no call keeps a caller pointer. Handles are owned
+ *    by the library and released with the matching *_free call.
+ *  - Device pointers are HIP device pointers on the current device.
+ */
+#ifndef PCX_H
+#define PCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCX_OK 0
+#define PCX_PENDING 1
+#define PCX_ERR_INVALID (-1)    /* bad argument: widths, box (lo >= hi), D outside 1..16, NULL */
+#define PCX_ERR_OOM (-2)        /* device or host allocation failed */
+#define PCX_ERR_DEGENERATE (-3) /* input not generic (Sec. 3.2, 3.4): a vertex on a hyperplane,
+                                   or a splitting 2-face not met by exactly two splitting edges */
+#define PCX_ERR_DEVICE (-4)     /* a HIP runtime call failed */
+#define PCX_ERR_CAPACITY (-5)   /* result would exceed pcx_opts.max_bytes */
+
+typedef struct pcx_mlp pcx_mlp;
+typedef struct pcx_complex pcx_complex;
+
+/* Options of one extraction. A zeroed struct (or NULL) gives the defaults. */
+typedef struct {
+    int32_t include_output; /* 1: subdivide the output neurons too (zero level set, Sec. 5.4) */
+    int32_t timing;         /* 1: time each kernel family with HIP events (pcx_complex_kernel_time) */
+    int32_t reserved0;
+    int32_t reserved1;
+    uint64_t max_bytes;     /* cap on device bytes the extraction may hold; 0 = no cap */
+    void *stream;           /* hipStream_t to run on; NULL = the default stream */
+} pcx_opts;
+
+/* Summary of an extracted complex. */
+typedef struct {
+    int64_t V;              /* vertices */
+    int64_t E;              /* edges */
+    int32_t D;              /* input dimension */
+    int32_t M;              /* sign-vector entries: 2D + subdivided neurons */
+    int32_t Wd;             /* uint64 words per packed sign-vector row */
+    int32_t n_steps;        /* subdivided neurons (one step each) */
+    int64_t total_splits;   /* sum over steps of splitting edges (= new vertices) */
+    int64_t total_pairs;    /* sum over steps of intersecting edges (step 5) */
+    uint64_t peak_bytes;    /* device bytes held at the peak of the extraction */
+    double time_ms;         /* device time of the extraction (HIP events, weights resident) */
+} pcx_info;
+
+const char *pcx_last_error(void);
+
+/* Copy a ReLU MLP to the device. widths has n_layers+1 entries (D first);
+ * W[l] points to N_{l+1} x N_l doubles (row-major), b[l] to N_{l+1} doubles,
+ * for l = 0 .. n_layers-1 (host pointers). Sec. 3.4 defines the network. */
+int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const *W,
+                   const double *const *b, pcx_mlp **out);
+void pcx_mlp_free(pcx_mlp *mlp);
+
+/* Edge subdivision of the box [lo, hi] (D host doubles each, lo < hi) by every
+ * subdivided neuron of mlp, in layer order (Sec. 4.2). On success *out owns
+ * the complex on the device. On error *out is NULL. Work is queued on
+ * opts->stream; the call returns when the complex is complete. */
+int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts,
+                pcx_complex **out);
+
+int pcx_complex_info(const pcx_complex *cx, pcx_info *info);
+
+/* Per-step counters, n_steps rows of 4 int64 (host buffer): vertices and
+ * edges before the step, splitting edges, and 2-face records (Sec. 4.2.2). */
+int pcx_complex_steps(const pcx_complex *cx, int64_t *steps);
+
+/* Copy the complex to caller-allocated host buffers (any may be NULL):
+ * coords V*D doubles, signs V*Wd uint64 (packing above), edges E*2 int32. */
+int pcx_complex_copy(const pcx_complex *cx, double *coords, uint64_t *signs, int32_t *edges);
+
+/* Borrowed device pointers to the same three arrays, valid until
+ * pcx_complex_free. Any out-pointer may be NULL. */
+int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void **edges);
+
+/* Kernel-family device time in milliseconds accumulated during an extraction
+ * run with opts.timing = 1: family is one of the PCX_K_* values below;
+ * *launches receives the number of launches timed. */
+#define PCX_K_GEMM 0     /* per-layer pre-activation evaluation (step 1) */
+#define PCX_K_NEXT 1     /* per-layer first-crossing scan of every edge (steps 2-3) */
+#define PCX_K_SELECT 2   /* per-step splitting-edge compaction (step 3) */
+#define PCX_K_SPLIT 3    /* per-step interpolation, split, 2-face keys (steps 4-5) */
+#define PCX_K_SORT 4     /* per-step radix sort of 2-face keys (step 5) */
+#define PCX_K_PAIR 5     /* per-step pairing into intersecting edges (step 5) */
+#define PCX_K_COUNT 6
+int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, int64_t *launches);
+
+void pcx_complex_free(pcx_complex *cx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCX_H */

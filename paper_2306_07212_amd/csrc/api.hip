@@ -1,0 +1,570 @@
+// Host side of libpcx.so: the C ABI of include/pcx.h and the orchestration of
+// edge subdivision (Berzins 2023, Sec. 4.2) on one GPU. Weights are copied to
+// the device once per network; an extraction keeps every array on the device
+// and crosses to the host once per neuron step to read four counters (the
+// number of splitting edges sizes the launches and the storage).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "pcx.h"
+
+using namespace pcx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                               \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) return fail(PCX_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+struct pcx_mlp {
+    int L = 0, D = 0;
+    std::vector<int> widths;
+    std::vector<double *> Wt;  // device, layer l: [N_{l-1}][N_l] (transposed for coalesced GEMM reads)
+    std::vector<double *> b;   // device, [N_l]
+    std::atomic<int64_t> hintV{0}, hintE{0};  // sizes seen by the last extraction (capacity hint)
+};
+
+struct pcx_complex {
+    int D = 0, M = 0, Wd = 0, n_steps = 0;
+    int64_t V = 0, E = 0;
+    double *X = nullptr;
+    uint64_t *SG = nullptr;
+    int2 *EDG = nullptr;
+    std::vector<int64_t> steps;
+    int64_t total_splits = 0, total_pairs = 0;
+    uint64_t peak = 0;
+    double time_ms = 0.0;
+    double ktime[PCX_K_COUNT] = {};
+    int64_t klaunch[PCX_K_COUNT] = {};
+};
+
+namespace {
+
+// Device memory of one extraction, with a byte cap and peak accounting.
+struct Arena {
+    uint64_t cap = 0, cur = 0, peak = 0;
+    std::vector<std::pair<void *, size_t>> live;
+    int alloc(void **p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 256;
+        if (cap && cur + bytes > cap)
+            return fail(PCX_ERR_CAPACITY, "extraction needs more device memory than max_bytes allows");
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PCX_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        live.push_back({*p, bytes});
+        cur += bytes;
+        peak = std::max(peak, cur);
+        return PCX_OK;
+    }
+    void release(void *p) {
+        if (!p) return;
+        for (size_t i = 0; i < live.size(); ++i)
+            if (live[i].first == p) {
+                cur -= live[i].second;
+                live.erase(live.begin() + i);
+                (void)hipFree(p);
+                return;
+            }
+    }
+    void forget(void *p) {  // ownership moves out (to a pcx_complex)
+        for (size_t i = 0; i < live.size(); ++i)
+            if (live[i].first == p) {
+                live.erase(live.begin() + i);
+                return;
+            }
+    }
+    ~Arena() {
+        for (auto &a : live) (void)hipFree(a.first);
+    }
+};
+
+struct EventPool {
+    std::vector<hipEvent_t> free_, all_;
+    struct Pending { hipEvent_t a, b; int fam; };
+    std::vector<Pending> pend;
+    hipEvent_t get() {
+        if (free_.empty()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            all_.push_back(e);
+            return e;
+        }
+        hipEvent_t e = free_.back();
+        free_.pop_back();
+        return e;
+    }
+    ~EventPool() {
+        for (auto e : all_) (void)hipEventDestroy(e);
+    }
+};
+
+struct Extraction {
+    const pcx_mlp *mlp;
+    hipStream_t st;
+    bool timing;
+    Arena arena;
+    Bufs b{};
+    size_t Vcap = 0, Ecap = 0, Scap = 0, Kcap = 0, Hcap = 0, SELcap = 0;
+    int D = 0, Wd = 0, ZS = 0, P = 0;
+    int *hctr = nullptr;  // pinned
+    EventPool ev;
+    double ktime[PCX_K_COUNT] = {};
+    int64_t klaunch[PCX_K_COUNT] = {};
+
+    ~Extraction() {
+        if (hctr) (void)hipHostFree(hctr);
+    }
+
+    int mark(int fam, bool start) {
+        if (!timing) return PCX_OK;
+        hipEvent_t e = ev.get();
+        if (!e) return fail(PCX_ERR_DEVICE, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(e, st));
+        if (start) {
+            ev.pend.push_back({e, nullptr, fam});
+        } else {
+            ev.pend.back().b = e;
+        }
+        return PCX_OK;
+    }
+    int collect() {  // after a stream synchronisation
+        for (auto &p : ev.pend) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+            ktime[p.fam] += ms;
+            klaunch[p.fam] += 1;
+            ev.free_.push_back(p.a);
+            ev.free_.push_back(p.b);
+        }
+        ev.pend.clear();
+        return PCX_OK;
+    }
+
+    // grow an array whose first `used` elements must survive
+    template <class T>
+    int grow_keep(T *&p, size_t &cap, size_t need, size_t used, size_t per) {
+        if (need <= cap) return PCX_OK;
+        size_t nc = std::max(need, cap + cap / 2);
+        void *q;
+        int rc = arena.alloc(&q, nc * per * sizeof(T));
+        if (rc) return rc;
+        if (p && used) HIPCHK(hipMemcpyAsync(q, p, used * per * sizeof(T), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        arena.release(p);
+        p = (T *)q;
+        cap = nc;
+        return PCX_OK;
+    }
+    template <class T>
+    int grow_scratch(T *&p, size_t cap, size_t nc) {  // contents need not survive
+        if (p) HIPCHK(hipStreamSynchronize(st));
+        arena.release(p);
+        void *q;
+        int rc = arena.alloc(&q, nc * sizeof(T));
+        if (rc) return rc;
+        p = (T *)q;
+        (void)cap;
+        return PCX_OK;
+    }
+
+    int ensure_vertices(size_t need, size_t used) {
+        if (need <= Vcap) return PCX_OK;
+        size_t c0 = Vcap, c1 = Vcap, c2 = Vcap;
+        int rc;
+        if ((rc = grow_keep(b.X, c0, need, used, (size_t)D))) return rc;
+        if ((rc = grow_keep(b.SG, c1, need, used, (size_t)Wd))) return rc;
+        if ((rc = grow_keep(b.Z, c2, need, used, (size_t)ZS))) return rc;
+        Vcap = std::min(c0, std::min(c1, c2));
+        return PCX_OK;
+    }
+    // spl_used: split ids already written by this step's compaction (kept)
+    int ensure_edges(size_t need, size_t used, size_t spl_used) {
+        if (need <= Ecap) return PCX_OK;
+        size_t c0 = Ecap, c1 = Ecap;
+        int rc;
+        if ((rc = grow_keep(b.EDG, c0, need, used, 1))) return rc;
+        if ((rc = grow_keep(b.NXT, c1, need, used, 1))) return rc;
+        Ecap = std::min(c0, c1);
+        // the compaction writes up to E split ids before the host learns S,
+        // so the split list always has the edge capacity
+        if (Ecap > Scap) {
+            size_t c2 = Scap;
+            if ((rc = grow_keep(b.SPL, c2, Ecap, spl_used, 1))) return rc;
+            Scap = c2;
+        }
+        size_t sel = Ecap / kSelTile + 2;
+        if (sel > SELcap) {
+            if ((rc = grow_scratch(b.SELST, SELcap, sel))) return rc;
+            HIPCHK(hipMemsetAsync(b.SELST, 0, sel * sizeof(uint64_t), st));
+            SELcap = sel;
+        }
+        return PCX_OK;
+    }
+    int ensure_step(size_t S, size_t K) {
+        int rc;
+        if (S > Scap) return fail(PCX_ERR_DEVICE, "split list smaller than the split count");
+        if (K > Kcap) {
+            size_t nc = std::max(K, Kcap * 2);
+            if ((rc = grow_scratch(b.K32a, Kcap, nc))) return rc;
+            if ((rc = grow_scratch(b.K32b, Kcap, nc))) return rc;
+            if ((rc = grow_scratch(b.VALa, Kcap, nc))) return rc;
+            if ((rc = grow_scratch(b.VALb, Kcap, nc))) return rc;
+            if ((rc = grow_scratch(b.FULL, Kcap, nc))) return rc;
+            if ((rc = grow_scratch(b.PINFO, Kcap, nc))) return rc;
+            Kcap = nc;
+        }
+        size_t h = (size_t)kSortBins * ((K + kSortTile - 1) / kSortTile + 1);
+        if (h > Hcap) {
+            size_t nc = std::max(h, Hcap * 2);
+            if ((rc = grow_scratch(b.HIST, Hcap, nc))) return rc;
+            Hcap = nc;
+        }
+        return PCX_OK;
+    }
+};
+
+int degenerate_message(int flags) {
+    std::string m = "input is not generic:";
+    if (flags & FLAG_ZERO_SIGN) m += " a vertex lies on a hyperplane;";
+    if (flags & FLAG_CONFLICT) m += " sign conflict on an edge;";
+    if (flags & FLAG_ZERO_COUNT) m += " a splitting edge without D-1 zeros;";
+    if (flags & FLAG_RUN) m += " a 2-face not met by exactly two splitting edges;";
+    if (flags & FLAG_VERIFY) m += " 2-face hashes equal but sign-vectors differ;";
+    if (flags & FLAG_BOUNDS) return fail(PCX_ERR_DEVICE, "internal error: a kernel saw an index out of range");
+    return fail(PCX_ERR_DEGENERATE, m);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pcx_last_error(void) { return g_err.c_str(); }
+
+int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const *W, const double *const *b,
+                   pcx_mlp **out) {
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_layers < 1 || !widths || !W || !b) return fail(PCX_ERR_INVALID, "bad network description");
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 1) return fail(PCX_ERR_INVALID, "every width must be >= 1");
+    if (widths[0] > 16) return fail(PCX_ERR_INVALID, "input dimension D must be 1..16");
+    pcx_mlp *m = new pcx_mlp();
+    m->L = n_layers;
+    m->D = widths[0];
+    m->widths.assign(widths, widths + n_layers + 1);
+    std::vector<double> tmp;
+    for (int l = 0; l < n_layers; ++l) {
+        const int nin = widths[l], nout = widths[l + 1];
+        if (!W[l] || !b[l]) {
+            pcx_mlp_free(m);
+            return fail(PCX_ERR_INVALID, "NULL weight or bias pointer");
+        }
+        tmp.resize((size_t)nin * nout);
+        for (int i = 0; i < nout; ++i)
+            for (int k = 0; k < nin; ++k) tmp[(size_t)k * nout + i] = W[l][(size_t)i * nin + k];
+        double *dw = nullptr, *db = nullptr;
+        if (hipMalloc((void **)&dw, tmp.size() * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&db, (size_t)nout * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (dw) (void)hipFree(dw);
+            pcx_mlp_free(m);
+            return fail(PCX_ERR_OOM, "hipMalloc for weights failed");
+        }
+        m->Wt.push_back(dw);
+        m->b.push_back(db);
+        if (hipMemcpy(dw, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(db, b[l], (size_t)nout * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            pcx_mlp_free(m);
+            return fail(PCX_ERR_DEVICE, "copying weights to the device failed");
+        }
+    }
+    *out = m;
+    return PCX_OK;
+}
+
+void pcx_mlp_free(pcx_mlp *m) {
+    if (!m) return;
+    for (auto p : m->Wt) (void)hipFree(p);
+    for (auto p : m->b) (void)hipFree(p);
+    delete m;
+}
+
+int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out) {
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!mlp || !lo || !hi) return fail(PCX_ERR_INVALID, "NULL argument");
+    pcx_opts o{};
+    if (opts) o = *opts;
+    const int D = mlp->D, L = mlp->L;
+    for (int j = 0; j < D; ++j)
+        if (!(lo[j] < hi[j])) return fail(PCX_ERR_INVALID, "box must have lo < hi in every coordinate");
+    const int nsub = o.include_output ? L : L - 1;
+    std::vector<int> lw(nsub + 1);
+    lw[0] = 1;
+    int M = 2 * D, ZS = 1, n_steps = 0;
+    for (int l = 0; l < nsub; ++l) {
+        const int N = mlp->widths[l + 1];
+        if (N > kMaxWidth) return fail(PCX_ERR_INVALID, "subdivided layers wider than 256 are not supported");
+        if (N >= (int)kNone) return fail(PCX_ERR_INVALID, "layer too wide");
+        lw[l + 1] = lw[l] + (N + 31) / 32;
+        M += N;
+        ZS = std::max(ZS, N);
+        n_steps += N;
+    }
+    const int Wd = lw[nsub];
+
+    Extraction x;
+    x.mlp = mlp;
+    x.st = (hipStream_t)o.stream;
+    x.timing = o.timing != 0;
+    x.arena.cap = o.max_bytes;
+    x.D = D;
+    x.Wd = Wd;
+    x.ZS = ZS;
+    x.P = D >= 2 ? 2 * (D - 1) : 0;
+    hipStream_t st = x.st;
+    int rc;
+
+    // host-side tables
+    std::vector<uint64_t> valid(Wd, 0);
+    for (int e = 0; e < 2 * D; ++e) valid[0] |= 1ull << (2 * e);
+    for (int l = 0; l < nsub; ++l)
+        for (int c = 0; c < mlp->widths[l + 1]; ++c) valid[lw[l] + (c >> 5)] |= 1ull << (2 * (c & 31));
+
+    const size_t V0 = (size_t)1 << D, E0 = (size_t)D << (D - 1);
+    HIPCHK(hipHostMalloc((void **)&x.hctr, CTR_COUNT * sizeof(int), hipHostMallocDefault));
+    {
+        void *p;
+        if ((rc = x.arena.alloc(&p, CTR_COUNT * sizeof(int)))) return rc;
+        x.b.CTR = (int *)p;
+        if ((rc = x.arena.alloc(&p, Wd * sizeof(uint64_t)))) return rc;
+        x.b.VALID = (const uint64_t *)p;
+        HIPCHK(hipMemcpyAsync(p, valid.data(), Wd * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        if ((rc = x.arena.alloc(&p, (size_t)(n_steps + 2) * sizeof(int)))) return rc;
+        x.b.TICKETS = (int *)p;
+        HIPCHK(hipMemsetAsync(p, 0, (size_t)(n_steps + 2) * sizeof(int), st));
+    }
+    double *dbox;
+    {
+        void *p;
+        if ((rc = x.arena.alloc(&p, 2 * D * sizeof(double)))) return rc;
+        dbox = (double *)p;
+        HIPCHK(hipMemcpyAsync(dbox, lo, D * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dbox + D, hi, D * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    if ((rc = x.ensure_vertices(std::max<size_t>({V0, 1024, (size_t)mlp->hintV.load()}), 0))) return rc;
+    if ((rc = x.ensure_edges(std::max<size_t>({E0, 4096, (size_t)mlp->hintE.load()}), 0, 0))) return rc;
+    {
+        int h[CTR_COUNT] = {0};
+        h[CTR_E] = (int)E0;
+        std::memcpy(x.hctr, h, sizeof h);
+        HIPCHK(hipMemcpyAsync(x.b.CTR, x.hctr, sizeof h, hipMemcpyHostToDevice, st));
+    }
+
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evg{t0, t1};
+    HIPCHK(hipEventRecord(t0, st));
+    launch_init_box(x.b, D, Wd, dbox, dbox + D, st);
+    HIPCHK(hipGetLastError());
+
+    std::vector<int64_t> steps((size_t)n_steps * 4, 0);
+    int64_t V = (int64_t)V0, E = (int64_t)E0;
+    int64_t prevE = -1, prevS = 0;
+    int step = 0;
+    uint32_t epoch = 0;
+    int64_t total_splits = 0;
+    for (int l = 0; l < nsub; ++l) {
+        const int N = mlp->widths[l + 1], K = mlp->widths[l];
+        // step 1 for the whole layer: pre-activations at every vertex
+        if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
+        if (l == 0)
+            launch_gemm(x.b, ZS, x.b.X, D, 0, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+        else
+            launch_gemm(x.b, ZS, x.b.Z, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+        if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
+        if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
+        launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, st);
+        if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
+        HIPCHK(hipGetLastError());
+        for (int j = 0; j < N; ++j, ++step) {
+            ++epoch;
+            const int64_t Emax = prevE < 0 ? E : E + prevS * (int64_t)D;
+            if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
+            launch_select(x.b, (uint16_t)j, epoch, (int)std::min<int64_t>(Emax, (int64_t)x.Ecap), st);
+            if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if ((rc = x.collect())) return rc;
+            if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
+            const int64_t S = x.hctr[CTR_S];
+            E = x.hctr[CTR_E];
+            if (step > 0) steps[(size_t)(step - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+            steps[(size_t)step * 4 + 0] = V;
+            steps[(size_t)step * 4 + 1] = E;
+            steps[(size_t)step * 4 + 2] = S;
+            prevE = E;
+            prevS = S;
+            if (S == 0) continue;
+            const int64_t Eneed = E + S + S * std::max(0, D - 1);
+            if (V + S >= INT32_MAX || Eneed >= INT32_MAX)
+                return fail(PCX_ERR_CAPACITY, "complex exceeds 2^31 vertices or edges");
+            if ((rc = x.ensure_vertices((size_t)(V + S), (size_t)V))) return rc;
+            if ((rc = x.ensure_edges((size_t)Eneed, (size_t)E, (size_t)S))) return rc;
+            if ((rc = x.ensure_step((size_t)S, (size_t)S * x.P))) return rc;
+            StepGeom g;
+            g.D = D;
+            g.Wd = Wd;
+            g.ZS = ZS;
+            g.Nl = N;
+            g.lw0 = lw[l];
+            g.lw1 = lw[l + 1];
+            g.j = j;
+            g.wn = lw[l] + (j >> 5);
+            g.bn = 2 * (j & 31);
+            g.P = x.P;
+            if ((rc = x.mark(PCX_K_SPLIT, true))) return rc;
+            launch_split(x.b, g, (int)V, (int)E, (int)S, st);
+            if ((rc = x.mark(PCX_K_SPLIT, false))) return rc;
+            HIPCHK(hipGetLastError());
+            if (x.P > 0) {
+                if ((rc = x.mark(PCX_K_SORT, true))) return rc;
+                launch_sort(x.b, (int)(S * x.P), st);
+                if ((rc = x.mark(PCX_K_SORT, false))) return rc;
+                HIPCHK(hipGetLastError());
+                if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
+                launch_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), st);
+                if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
+                HIPCHK(hipGetLastError());
+            } else {
+                x.hctr[CTR_E] = (int)(E + S);
+                HIPCHK(hipMemcpyAsync(x.b.CTR + CTR_E, x.hctr + CTR_E, sizeof(int), hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
+            V += S;
+            total_splits += S;
+        }
+    }
+    HIPCHK(hipEventRecord(t1, st));
+    HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if ((rc = x.collect())) return rc;
+    if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
+    E = x.hctr[CTR_E];
+    if (step > 0) steps[(size_t)(step - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+
+    pcx_complex *cx = new pcx_complex();
+    cx->D = D;
+    cx->M = M;
+    cx->Wd = Wd;
+    cx->n_steps = n_steps;
+    cx->V = V;
+    cx->E = E;
+    cx->X = x.b.X;
+    cx->SG = x.b.SG;
+    cx->EDG = x.b.EDG;
+    x.arena.forget(x.b.X);
+    x.arena.forget(x.b.SG);
+    x.arena.forget(x.b.EDG);
+    cx->steps = std::move(steps);
+    cx->total_splits = total_splits;
+    int64_t pairs = 0;
+    for (int s = 0; s < n_steps; ++s) pairs += cx->steps[(size_t)s * 4 + 3] / 2;
+    cx->total_pairs = pairs;
+    cx->peak = x.arena.peak;
+    cx->time_ms = ms;
+    for (int k = 0; k < PCX_K_COUNT; ++k) {
+        cx->ktime[k] = x.ktime[k];
+        cx->klaunch[k] = x.klaunch[k];
+    }
+    auto *m = const_cast<pcx_mlp *>(mlp);
+    m->hintV.store(std::max<int64_t>(m->hintV.load(), V));
+    m->hintE.store(std::max<int64_t>(m->hintE.load(), E));
+    *out = cx;
+    return PCX_OK;
+}
+
+int pcx_complex_info(const pcx_complex *cx, pcx_info *info) {
+    if (!cx || !info) return fail(PCX_ERR_INVALID, "NULL argument");
+    info->V = cx->V;
+    info->E = cx->E;
+    info->D = cx->D;
+    info->M = cx->M;
+    info->Wd = cx->Wd;
+    info->n_steps = cx->n_steps;
+    info->total_splits = cx->total_splits;
+    info->total_pairs = cx->total_pairs;
+    info->peak_bytes = cx->peak;
+    info->time_ms = cx->time_ms;
+    return PCX_OK;
+}
+
+int pcx_complex_steps(const pcx_complex *cx, int64_t *steps) {
+    if (!cx || !steps) return fail(PCX_ERR_INVALID, "NULL argument");
+    std::memcpy(steps, cx->steps.data(), cx->steps.size() * sizeof(int64_t));
+    return PCX_OK;
+}
+
+int pcx_complex_copy(const pcx_complex *cx, double *coords, uint64_t *signs, int32_t *edges) {
+    if (!cx) return fail(PCX_ERR_INVALID, "NULL complex");
+    if (coords) HIPCHK(hipMemcpy(coords, cx->X, (size_t)cx->V * cx->D * sizeof(double), hipMemcpyDeviceToHost));
+    if (signs) HIPCHK(hipMemcpy(signs, cx->SG, (size_t)cx->V * cx->Wd * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (edges) HIPCHK(hipMemcpy(edges, cx->EDG, (size_t)cx->E * 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return PCX_OK;
+}
+
+int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void **edges) {
+    if (!cx) return fail(PCX_ERR_INVALID, "NULL complex");
+    if (coords) *coords = cx->X;
+    if (signs) *signs = cx->SG;
+    if (edges) *edges = cx->EDG;
+    return PCX_OK;
+}
+
+int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, int64_t *launches) {
+    if (!cx || family < 0 || family >= PCX_K_COUNT) return fail(PCX_ERR_INVALID, "bad argument");
+    if (ms) *ms = cx->ktime[family];
+    if (launches) *launches = cx->klaunch[family];
+    return PCX_OK;
+}
+
+void pcx_complex_free(pcx_complex *cx) {
+    if (!cx) return;
+    (void)hipFree(cx->X);
+    (void)hipFree(cx->SG);
+    (void)hipFree(cx->EDG);
+    delete cx;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Internal declarations shared by the kernels and the host orchestrator of
+// libpcx.so. Not part of the public ABI (include/pcx.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcx {
+
+constexpr int kThreads = 256;            // every kernel uses 256-thread workgroups (4 waves)
+constexpr int kSelItems = 16;            // edges per thread in the compaction scan
+constexpr int kSelTile = kThreads * kSelItems;
+constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile
+constexpr int kSortTile = kThreads * kSortItems;
+constexpr int kSortBins = 256;           // 8-bit digits, 4 passes over 32-bit keys
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // key of an unused 2-face slot (valid keys < 2^31)
+constexpr uint16_t kNone = 0xFFFF;       // "no further crossing in this layer"
+constexpr int kGemmRows = 32;            // vertices per GEMM workgroup
+constexpr int kGemmK = 16;               // K-chunk staged in LDS
+constexpr int kMaxWidth = 256;           // widest layer the in-place GEMM handles
+
+// device counters (int32 slots of one small array)
+enum { CTR_S = 0, CTR_KVALID = 1, CTR_E = 2, CTR_FLAGS = 3, CTR_COUNT = 8 };
+
+// degeneracy / failure flags (bitwise)
+enum : int {
+    FLAG_ZERO_SIGN = 1,   // a pre-activation exactly 0 at a vertex where the neuron is not zero by construction
+    FLAG_CONFLICT = 2,    // +/- conflict in the join of a splitting edge's endpoints
+    FLAG_ZERO_COUNT = 4,  // splitting edge without exactly D-1 zeros
+    FLAG_RUN = 8,         // a 2-face key met by other than exactly two splitting edges
+    FLAG_VERIFY = 16,     // equal hashes but different exact 2-face sign-vectors
+    FLAG_BOUNDS = 32,     // an index outside the live arrays (internal error; the access is skipped)
+};
+
+// Geometry of one neuron step (layer l, neuron j of that layer).
+struct StepGeom {
+    int D, Wd, ZS;   // input dim, words per sign row, pre-activation row stride
+    int Nl;          // width of the layer being subdivided
+    int lw0, lw1;    // first word of this layer's entries, first word of the next layer
+    int j;           // neuron within the layer
+    int wn, bn;      // word and bit offset of this neuron's entry
+    int P;           // 2-face key slots per split: 2(D-1)
+};
+
+struct Bufs {
+    double *X;        // [Vcap][D]
+    uint64_t *SG;     // [Vcap][Wd]
+    double *Z;        // [Vcap][ZS]
+    int2 *EDG;        // [Ecap]
+    uint16_t *NXT;    // [Ecap]
+    int *SPL;         // [Scap]
+    uint32_t *K32a, *K32b, *VALa, *VALb;  // [Kcap] radix-sort ping-pong
+    uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot
+    uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus
+    uint32_t *HIST;   // [256 * tiles]
+    uint64_t *SELST;  // [Ecap / kSelTile + 1] decoupled look-back status
+    int *TICKETS;     // [n_epochs] dynamic tile tickets, one counter per compaction launch
+    int *CTR;         // [CTR_COUNT]
+    const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
+};
+
+// launchers (kernels.hip)
+void launch_init_box(const Bufs &b, int D, int Wd, const double *lo, const double *hi, hipStream_t st);
+void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int relu, int V, int K, int N,
+                 const double *Wt, const double *bias, int Wd, int lw0, hipStream_t st);
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ecap_hint, hipStream_t st);
+void launch_select(const Bufs &b, uint16_t target, uint32_t epoch, int Emax, hipStream_t st);
+void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st);
+void launch_sort(const Bufs &b, int n, hipStream_t st);  // result in K32a/VALa
+void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st);
+
+}  // namespace pcx

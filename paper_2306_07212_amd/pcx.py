@@ -1,0 +1,223 @@
+"""ctypes binding of libpcx.so (same names as the C ABI in include/pcx.h).
+
+Argument marshalling only: networks are copied to the device by
+``pcx_mlp_create``, the extraction runs entirely in the library's HIP kernels,
+and results are copied back on request. Importing this module without the
+built library raises ``ImportError``: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcx.so")
+
+PCX_OK, PCX_PENDING = 0, 1
+PCX_ERR_INVALID, PCX_ERR_OOM, PCX_ERR_DEGENERATE, PCX_ERR_DEVICE, PCX_ERR_CAPACITY = -1, -2, -3, -4, -5
+KERNEL_FAMILIES = ["gemm", "next", "select", "split", "sort", "pair"]
+
+# every symbol include/pcx.h declares
+SYMBOLS = [
+    "pcx_last_error", "pcx_mlp_create", "pcx_mlp_free", "pcx_extract", "pcx_complex_info",
+    "pcx_complex_steps", "pcx_complex_copy", "pcx_complex_device", "pcx_complex_kernel_time",
+    "pcx_complex_free",
+]
+
+
+class PcxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pcx error {code}: {msg}")
+        self.code = code
+
+
+class _Opts(C.Structure):
+    _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("V", C.c_int64), ("E", C.c_int64), ("D", C.c_int32), ("M", C.c_int32), ("Wd", C.c_int32),
+                ("n_steps", C.c_int32), ("total_splits", C.c_int64), ("total_pairs", C.c_int64),
+                ("peak_bytes", C.c_uint64), ("time_ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2306_07212_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    PD = C.POINTER(C.c_double)
+    lib.pcx_last_error.restype = C.c_char_p
+    lib.pcx_mlp_create.argtypes = [i32, C.POINTER(i32), C.POINTER(PD), C.POINTER(PD), C.POINTER(vp)]
+    lib.pcx_mlp_free.argtypes = [vp]
+    lib.pcx_mlp_free.restype = None
+    lib.pcx_extract.argtypes = [vp, PD, PD, C.POINTER(_Opts), C.POINTER(vp)]
+    lib.pcx_complex_info.argtypes = [vp, C.POINTER(_Info)]
+    lib.pcx_complex_steps.argtypes = [vp, vp]
+    lib.pcx_complex_copy.argtypes = [vp, vp, vp, vp]
+    lib.pcx_complex_device.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+    lib.pcx_complex_kernel_time.argtypes = [vp, i32, PD, C.POINTER(i64)]
+    lib.pcx_complex_free.argtypes = [vp]
+    lib.pcx_complex_free.restype = None
+    for s in SYMBOLS:
+        getattr(lib, s)
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int):
+    if rc != PCX_OK:
+        raise PcxError(rc, _lib.pcx_last_error().decode())
+
+
+def last_error() -> str:
+    return _lib.pcx_last_error().decode()
+
+
+class MLP:
+    """A ReLU MLP on the device (``pcx_mlp_create``). W[l] is [N_l, N_{l-1}]."""
+
+    def __init__(self, widths: Sequence[int], W, b):
+        self.widths = [int(w) for w in widths]
+        L = len(self.widths) - 1
+        Wc = [np.ascontiguousarray(w, np.float64) for w in W]
+        bc = [np.ascontiguousarray(x, np.float64) for x in b]
+        if len(Wc) != L or len(bc) != L:
+            raise ValueError("need one W and one b per layer")
+        for l in range(L):
+            if Wc[l].shape != (self.widths[l + 1], self.widths[l]) or bc[l].shape != (self.widths[l + 1],):
+                raise ValueError(f"layer {l}: W must be [{self.widths[l + 1]}, {self.widths[l]}]")
+        PD = C.POINTER(C.c_double)
+        wa = (PD * L)(*[w.ctypes.data_as(PD) for w in Wc])
+        ba = (PD * L)(*[x.ctypes.data_as(PD) for x in bc])
+        ws = (C.c_int32 * (L + 1))(*self.widths)
+        h = C.c_void_p()
+        _check(_lib.pcx_mlp_create(L, ws, wa, ba, C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_net(cls, net) -> "MLP":
+        return cls(net.widths, net.W, net.b)
+
+    @property
+    def D(self) -> int:
+        return self.widths[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pcx_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+@dataclass
+class Info:
+    V: int
+    E: int
+    D: int
+    M: int
+    Wd: int
+    n_steps: int
+    total_splits: int
+    total_pairs: int
+    peak_bytes: int
+    time_ms: float
+
+
+def sign_layout(widths: Sequence[int], include_output: bool = False):
+    """(word, shift) of every sign-vector entry under the packing of pcx.h:
+    box entries in word 0, each subdivided layer from a fresh word."""
+    D = int(widths[0])
+    L = len(widths) - 1
+    nsub = L if include_output else L - 1
+    word = [0] * (2 * D)
+    shift = [2 * e for e in range(2 * D)]
+    lw = 1
+    for l in range(1, nsub + 1):
+        for i in range(int(widths[l])):
+            word.append(lw + (i >> 5))
+            shift.append(2 * (i & 31))
+        lw += (int(widths[l]) + 31) // 32
+    return np.array(word, np.int64), np.array(shift, np.int64), lw
+
+
+class Complex:
+    """An extracted 1-skeleton held on the device (``pcx_complex``)."""
+
+    def __init__(self, handle, widths, include_output):
+        self._h = handle
+        self.widths = list(widths)
+        self.include_output = include_output
+
+    def info(self) -> Info:
+        i = _Info()
+        _check(_lib.pcx_complex_info(self._h, C.byref(i)))
+        return Info(i.V, i.E, i.D, i.M, i.Wd, i.n_steps, i.total_splits, i.total_pairs, i.peak_bytes, i.time_ms)
+
+    def steps(self) -> np.ndarray:
+        n = self.info().n_steps
+        out = np.zeros((n, 4), np.int64)
+        _check(_lib.pcx_complex_steps(self._h, out.ctypes.data))
+        return out
+
+    def copy(self):
+        """(coords [V, D] float64, packed signs [V, Wd] uint64, edges [E, 2] int32) on the host."""
+        inf = self.info()
+        X = np.empty((inf.V, inf.D), np.float64)
+        SG = np.empty((inf.V, inf.Wd), np.uint64)
+        Ed = np.empty((inf.E, 2), np.int32)
+        _check(_lib.pcx_complex_copy(self._h, X.ctypes.data, SG.ctypes.data, Ed.ctypes.data))
+        return X, SG, Ed
+
+    def signs(self, packed: Optional[np.ndarray] = None) -> np.ndarray:
+        """Sign-vectors as int8 [V, M] in {+1, 0, -1}."""
+        if packed is None:
+            _, packed, _ = self.copy()
+        word, shift, _ = sign_layout(self.widths, self.include_output)
+        codes = (packed[:, word] >> shift.astype(np.uint64)) & np.uint64(3)
+        out = np.zeros(codes.shape, np.int8)
+        out[codes == 1] = 1
+        out[codes == 2] = -1
+        return out
+
+    def device_pointers(self):
+        a, b, c = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        _check(_lib.pcx_complex_device(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def kernel_time(self, family: str):
+        ms, n = C.c_double(), C.c_int64()
+        _check(_lib.pcx_complex_kernel_time(self._h, KERNEL_FAMILIES.index(family), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pcx_complex_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def extract(mlp: MLP, lo, hi, include_output: bool = False, timing: bool = False, stream=None,
+            max_bytes: int = 0) -> Complex:
+    """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron."""
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
+        raise ValueError("lo and hi must have D entries")
+    o = _Opts(int(bool(include_output)), int(bool(timing)), 0, 0, int(max_bytes), stream)
+    h = C.c_void_p()
+    PD = C.POINTER(C.c_double)
+    _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))
+    return Complex(h, mlp.widths, include_output)

@@ -11,19 +11,36 @@ import numpy as np
 from brute import entry_values, join
 
 
-def unpack_signs(packed: np.ndarray, M: int) -> np.ndarray:
-    """2-bit packed rows ([V, Wd] uint64; entry i at word i>>5, bits 2(i&31);
-    code 00 = 0, 01 = +, 10 = -) to int8 sign-vectors [V, M]."""
+def unpack_signs(packed: np.ndarray, widths, include_output=False) -> np.ndarray:
+    """Packed rows ([V, Wd] uint64) to int8 sign-vectors [V, M] in {+1, 0, -1}.
+
+    Packing of include/pcx.h: 2 bits per entry, 00 = 0, 01 = +, 10 = -; box
+    entry e in word 0 at bits 2e; neuron i of the l-th subdivided layer in word
+    lw_l + i // 32 at bits 2 (i % 32), with lw_1 = 1, lw_{l+1} = lw_l + ceil(N_l / 32)."""
     packed = np.ascontiguousarray(packed, dtype=np.uint64)
-    V, Wd = packed.shape
-    idx = np.arange(M)
-    words = packed[:, idx >> 5]
-    codes = (words >> (2 * (idx & 31)).astype(np.uint64)) & np.uint64(3)
-    out = np.zeros((V, M), np.int8)
-    out[codes == 1] = 1
-    out[codes == 2] = -1
+    D = int(widths[0])
+    L = len(widths) - 1
+    nsub = L if include_output else L - 1
+    cols = [(0, 2 * e) for e in range(2 * D)]
+    lw = 1
+    for l in range(1, nsub + 1):
+        n = int(widths[l])
+        cols += [(lw + i // 32, 2 * (i % 32)) for i in range(n)]
+        lw += -(-n // 32)
+    assert packed.shape[1] == lw, f"expected {lw} words per row, got {packed.shape[1]}"
+    word = np.array([c[0] for c in cols])
+    shift = np.array([c[1] for c in cols], dtype=np.uint64)
+    codes = (packed[:, word] >> shift) & np.uint64(3)
     if np.any(codes == 3):
         raise AssertionError("invalid sign code 11")
+    out = np.zeros(codes.shape, np.int8)
+    out[codes == 1] = 1
+    out[codes == 2] = -1
+    # bits outside every entry must be clear
+    used = np.zeros(lw, dtype=np.uint64)
+    for w, sh in cols:
+        used[w] |= np.uint64(3) << np.uint64(sh)
+    assert not np.any(packed & ~used), "bits set outside the entries"
     return out
 
 

@@ -1,0 +1,138 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact sign-vectors, vertex/edge counts, per-step counters and canonical
+edge incidence; FP64 coordinates within 1e-10 (absolute).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from checks import assert_same_complex, check_invariants, digest, unpack_signs
+from paper_2306_07212_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def pcx():
+    from paper_2306_07212_amd import pcx as P
+    return P
+
+
+def gpu_complex(pcx, net, box, include_output=False, **kw):
+    m = pcx.MLP.from_net(net)
+    cx = pcx.extract(m, box.lo, box.hi, include_output=include_output, **kw)
+    X, SG, Ed = cx.copy()
+    S = unpack_signs(SG, net.widths, include_output)
+    steps = cx.steps()
+    info = cx.info()
+    cx.close()
+    m.close()
+    return X, S, Ed, steps, info
+
+
+def _compare(oracle_lib, pcx, net, box, incl=False, invariants=True):
+    X, S, Ed, steps, info = gpu_complex(pcx, net, box, incl)
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=incl)
+    assert info.V == r.V and info.E == r.E
+    assert np.array_equal(steps, r.steps), "per-step counters differ"
+    assert_same_complex((X, S, Ed), (r.X, r.S, r.edges), coord_tol=1e-10)
+    if invariants:
+        check_invariants(net, box.lo, box.hi, X, S, Ed, include_output=incl)
+    return X, S, Ed
+
+
+def test_plain_small_matches_oracle_and_golden(oracle_lib, pcx):
+    net = wl.plain_small()
+    box = wl.cube(2)
+    X, S, Ed = _compare(oracle_lib, pcx, net, box)
+    g = json.load(open(os.path.join(GOLDEN, "plain_small.json")))
+    assert (len(X), len(Ed)) == (g["V"], g["E"])
+    assert digest(S, Ed) == g["digest"]
+
+
+@pytest.mark.parametrize("widths,seed,incl", [
+    ([1, 9, 9, 1], 101, False),
+    ([2, 16, 16, 16, 1], 102, False),
+    ([2, 40, 33, 1], 103, True),
+    ([3, 12, 12, 1], 104, False),
+    ([3, 24, 20, 1], 105, True),
+    ([4, 8, 8, 1], 106, False),
+    ([2, 70, 1], 107, False),        # layer spanning three sign words
+    ([3, 64, 1], 108, True),
+    ([2, 1, 1, 1], 109, False),       # width-1 layers
+])
+def test_small_nets_match_oracle(oracle_lib, pcx, widths, seed, incl):
+    net = wl.he_mlp(widths, seed)
+    _compare(oracle_lib, pcx, net, wl.cube(widths[0]), incl)
+
+
+def test_asymmetric_box(oracle_lib, pcx):
+    net = wl.he_mlp([3, 10, 10, 1], 111)
+    box = wl.Box(np.array([-0.7, -0.2, 0.1]), np.array([0.9, 0.5, 1.3]))
+    _compare(oracle_lib, pcx, net, box)
+
+
+def test_differentiable_small_matches_golden(oracle_lib, pcx):
+    net = wl.differentiable_small()
+    X, S, Ed = _compare(oracle_lib, pcx, net, wl.cube(3), incl=True)
+    g = json.load(open(os.path.join(GOLDEN, "differentiable_small.json")))
+    assert digest(S, Ed) == g["digest"]
+
+
+def test_differentiable_workload_matches_oracle(oracle_lib, pcx):
+    """3 -> 64 -> 64 -> 64 -> 1 with the output's zero level set: ~0.67M vertices."""
+    net = wl.differentiable()
+    box = wl.cube(3)
+    X, S, Ed, steps, info = gpu_complex(pcx, net, box, True)
+    g = json.load(open(os.path.join(GOLDEN, "differentiable.json")))
+    assert (info.V, info.E) == (g["V"], g["E"])
+    assert np.array_equal(steps, np.array(g["steps"]))
+    assert digest(S, Ed) == g["digest"]
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=True)
+    assert_same_complex((X, S, Ed), (r.X, r.S, r.edges), coord_tol=1e-10)
+
+
+def test_run_twice_bit_identical(pcx):
+    net = wl.he_mlp([3, 32, 32, 1], 121)
+    box = wl.cube(3)
+    a = gpu_complex(pcx, net, box)
+    b = gpu_complex(pcx, net, box)
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+
+
+def test_no_subdivided_layer_is_the_box(pcx):
+    net = wl.he_mlp([3, 1], 131)
+    X, S, Ed, steps, info = gpu_complex(pcx, net, wl.cube(3))
+    assert info.V == 8 and info.E == 12 and len(steps) == 0
+
+
+def test_degenerate_input_is_reported(oracle_lib, pcx):
+    """A hyperplane through two box corners is not generic (Sec. 3.2)."""
+    net = wl.Net([2, 1, 1], [np.array([[1.0, 1.0]]), np.array([[1.0]])], [np.array([0.0]), np.array([0.0])])
+    with pytest.raises(pcx.PcxError) as e:
+        gpu_complex(pcx, net, wl.cube(2))
+    assert e.value.code == pcx.PCX_ERR_DEGENERATE
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.extract(net, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
+
+
+def test_invalid_arguments(pcx):
+    net = wl.plain_small()
+    m = pcx.MLP.from_net(net)
+    with pytest.raises(pcx.PcxError) as e:
+        pcx.extract(m, np.array([1.0, 0.0]), np.array([1.0, 1.0]))
+    assert e.value.code == pcx.PCX_ERR_INVALID
+    with pytest.raises(pcx.PcxError) as e:
+        pcx.extract(m, np.array([-1.0, -1.0]), np.array([1.0, 1.0]), max_bytes=4096)
+    assert e.value.code == pcx.PCX_ERR_CAPACITY
+    wide = wl.he_mlp([2, 300, 1], 1)
+    mw = pcx.MLP.from_net(wide)
+    with pytest.raises(pcx.PcxError) as e:
+        pcx.extract(mw, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
+    assert e.value.code == pcx.PCX_ERR_INVALID
