@@ -56,7 +56,7 @@ typedef struct pcx_complex pcx_complex;
 /* Options of one extraction. A zeroed struct (or NULL) gives the defaults. */
 typedef struct {
     int32_t include_output; /* 1: subdivide the output neurons too (zero level set, Sec. 5.4) */
-    int32_t timing;         /* 1: time each kernel family with HIP events (pcx_complex_kernel_time) */
+    int32_t timing;         /* bit f set: time kernel family f (PCX_K_*) with HIP events on the stream */
     int32_t reserved0;
     int32_t reserved1;
     uint64_t max_bytes;     /* cap on device bytes the extraction may hold; 0 = no cap */
@@ -108,7 +108,7 @@ int pcx_complex_copy(const pcx_complex *cx, double *coords, uint64_t *signs, int
 int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void **edges);
 
 /* Kernel-family device time in milliseconds accumulated during an extraction
- * run with opts.timing = 1: family is one of the PCX_K_* values below;
+ * run with bit `family` of opts.timing set: family is one of the PCX_K_* values below;
  * *launches receives the number of launches timed. */
 #define PCX_K_GEMM 0     /* per-layer pre-activation evaluation (step 1) */
 #define PCX_K_NEXT 1     /* per-layer first-crossing scan of every edge (steps 2-3) */
@@ -117,9 +117,16 @@ int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void 
 #define PCX_K_SORT 4     /* per-step radix sort of 2-face keys (step 5) */
 #define PCX_K_PAIR 5     /* per-step pairing into intersecting edges (step 5) */
 #define PCX_K_COUNT 6
+#define PCX_K_ALL ((1 << PCX_K_COUNT) - 1)
 int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, int64_t *launches);
 
 void pcx_complex_free(pcx_complex *cx);
+
+/* Device blocks of finished extractions (scratch and freed complexes) are kept
+ * by the library for reuse by later extractions on the same device. This call
+ * returns every cached block of the current device to the HIP runtime. A
+ * failed allocation also trims the cache and retries once. */
+void pcx_cache_trim(void);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -58,6 +62,77 @@ struct pcx_complex {
 
 namespace {
 
+// Device blocks released by finished extractions are kept for reuse, per
+// device and size class, so that repeated extractions of large complexes do
+// not pay for hipMalloc / hipFree of tens of GB each time. pcx_cache_trim()
+// returns them to the runtime; a failed hipMalloc trims and retries once.
+struct Pool {
+    std::mutex m;
+    std::map<std::pair<int, size_t>, std::vector<void *>> cached;  // (device, bytes) -> blocks
+    std::unordered_map<void *, std::pair<int, size_t>> owned;       // every block handed out
+    uint64_t cached_bytes = 0;
+
+    static size_t size_class(size_t bytes) {
+        const size_t g = bytes >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
+        return (bytes + g - 1) / g * g;
+    }
+    void *get(size_t bytes, size_t *got) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const size_t sz = size_class(bytes);
+        *got = sz;
+        {
+            std::lock_guard<std::mutex> lk(m);
+            auto it = cached.find({dev, sz});
+            if (it != cached.end() && !it->second.empty()) {
+                void *p = it->second.back();
+                it->second.pop_back();
+                cached_bytes -= sz;
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            if (hipMalloc(&p, sz) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        std::lock_guard<std::mutex> lk(m);
+        owned[p] = {dev, sz};
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(m);
+        auto it = owned.find(p);
+        if (it == owned.end()) return;
+        cached[it->second].push_back(p);
+        cached_bytes += it->second.second;
+    }
+    void trim() {
+        std::lock_guard<std::mutex> lk(m);
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto &kv : cached) {
+            if (kv.first.first != cur) continue;
+            for (void *p : kv.second) {
+                (void)hipFree(p);
+                owned.erase(p);
+                cached_bytes -= kv.first.second;
+            }
+            kv.second.clear();
+        }
+    }
+};
+
+Pool &pool() {
+    static Pool *p = new Pool();  // never destroyed: the runtime may be gone at exit
+    return *p;
+}
+
 // Device memory of one extraction, with a byte cap and peak accounting.
 struct Arena {
     uint64_t cap = 0, cur = 0, peak = 0;
@@ -65,15 +140,14 @@ struct Arena {
     int alloc(void **p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 256;
-        if (cap && cur + bytes > cap)
+        const size_t sz = Pool::size_class(bytes);
+        if (cap && cur + sz > cap)
             return fail(PCX_ERR_CAPACITY, "extraction needs more device memory than max_bytes allows");
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(PCX_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-        }
-        live.push_back({*p, bytes});
-        cur += bytes;
+        size_t got = 0;
+        *p = pool().get(bytes, &got);
+        if (!*p) return fail(PCX_ERR_OOM, "hipMalloc of " + std::to_string(sz) + " bytes failed");
+        live.push_back({*p, got});
+        cur += got;
         peak = std::max(peak, cur);
         return PCX_OK;
     }
@@ -83,7 +157,7 @@ struct Arena {
             if (live[i].first == p) {
                 cur -= live[i].second;
                 live.erase(live.begin() + i);
-                (void)hipFree(p);
+                pool().put(p);
                 return;
             }
     }
@@ -95,7 +169,7 @@ struct Arena {
             }
     }
     ~Arena() {
-        for (auto &a : live) (void)hipFree(a.first);
+        for (auto &a : live) pool().put(a.first);
     }
 };
 
@@ -122,10 +196,10 @@ struct EventPool {
 struct Extraction {
     const pcx_mlp *mlp;
     hipStream_t st;
-    bool timing;
+    int timing_mask = 0;
     Arena arena;
     Bufs b{};
-    size_t Vcap = 0, Ecap = 0, Scap = 0, Kcap = 0, Hcap = 0, SELcap = 0;
+    size_t Vcap = 0, Ecap = 0, Scap = 0, Kcap = 0, Hcap = 0;
     int D = 0, Wd = 0, ZS = 0, P = 0;
     int *hctr = nullptr;  // pinned
     EventPool ev;
@@ -137,7 +211,7 @@ struct Extraction {
     }
 
     int mark(int fam, bool start) {
-        if (!timing) return PCX_OK;
+        if (!(timing_mask & (1 << fam))) return PCX_OK;
         hipEvent_t e = ev.get();
         if (!e) return fail(PCX_ERR_DEVICE, "hipEventCreate failed");
         HIPCHK(hipEventRecord(e, st));
@@ -212,12 +286,6 @@ struct Extraction {
             size_t c2 = Scap;
             if ((rc = grow_keep(b.SPL, c2, Ecap, spl_used, 1))) return rc;
             Scap = c2;
-        }
-        size_t sel = Ecap / kSelTile + 2;
-        if (sel > SELcap) {
-            if ((rc = grow_scratch(b.SELST, SELcap, sel))) return rc;
-            HIPCHK(hipMemsetAsync(b.SELST, 0, sel * sizeof(uint64_t), st));
-            SELcap = sel;
         }
         return PCX_OK;
     }
@@ -337,7 +405,7 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     Extraction x;
     x.mlp = mlp;
     x.st = (hipStream_t)o.stream;
-    x.timing = o.timing != 0;
+    x.timing_mask = o.timing;
     x.arena.cap = o.max_bytes;
     x.D = D;
     x.Wd = Wd;
@@ -361,9 +429,8 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
         if ((rc = x.arena.alloc(&p, Wd * sizeof(uint64_t)))) return rc;
         x.b.VALID = (const uint64_t *)p;
         HIPCHK(hipMemcpyAsync(p, valid.data(), Wd * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-        if ((rc = x.arena.alloc(&p, (size_t)(n_steps + 2) * sizeof(int)))) return rc;
-        x.b.TICKETS = (int *)p;
-        HIPCHK(hipMemsetAsync(p, 0, (size_t)(n_steps + 2) * sizeof(int), st));
+        if ((rc = x.arena.alloc(&p, (size_t)kSelBlocks * sizeof(int)))) return rc;
+        x.b.SELCNT = (int *)p;
     }
     double *dbox;
     {
@@ -400,10 +467,16 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     int64_t V = (int64_t)V0, E = (int64_t)E0;
     int64_t prevE = -1, prevS = 0;
     int step = 0;
-    uint32_t epoch = 0;
     int64_t total_splits = 0;
+    const char *verbose_env = getenv("PCX_VERBOSE");
+    const bool verbose = verbose_env && verbose_env[0] == '1';
     for (int l = 0; l < nsub; ++l) {
         const int N = mlp->widths[l + 1], K = mlp->widths[l];
+        if (verbose) {
+            fprintf(stderr, "[pcx] layer %d start: V=%lld E<=%lld device bytes=%llu peak=%llu\n", l + 1, (long long)V,
+                    (long long)(E + prevS * D), (unsigned long long)x.arena.cur, (unsigned long long)x.arena.peak);
+            fflush(stderr);
+        }
         // step 1 for the whole layer: pre-activations at every vertex
         if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
         if (l == 0)
@@ -416,10 +489,8 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
         if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
         HIPCHK(hipGetLastError());
         for (int j = 0; j < N; ++j, ++step) {
-            ++epoch;
-            const int64_t Emax = prevE < 0 ? E : E + prevS * (int64_t)D;
             if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-            launch_select(x.b, (uint16_t)j, epoch, (int)std::min<int64_t>(Emax, (int64_t)x.Ecap), st);
+            launch_select(x.b, (uint16_t)j, st);
             if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -561,10 +632,12 @@ int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, i
 
 void pcx_complex_free(pcx_complex *cx) {
     if (!cx) return;
-    (void)hipFree(cx->X);
-    (void)hipFree(cx->SG);
-    (void)hipFree(cx->EDG);
+    pool().put(cx->X);
+    pool().put(cx->SG);
+    pool().put(cx->EDG);
     delete cx;
 }
+
+void pcx_cache_trim(void) { pool().trim(); }
 
 }  // extern "C"

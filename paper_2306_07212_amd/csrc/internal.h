@@ -9,6 +9,7 @@ namespace pcx {
 constexpr int kThreads = 256;            // every kernel uses 256-thread workgroups (4 waves)
 constexpr int kSelItems = 16;            // edges per thread in the compaction scan
 constexpr int kSelTile = kThreads * kSelItems;
+constexpr int kSelBlocks = 1024;         // fixed grid of the two-pass compaction
 constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile
 constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kSortBins = 256;           // 8-bit digits, 4 passes over 32-bit keys
@@ -52,8 +53,7 @@ struct Bufs {
     uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot
     uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus
     uint32_t *HIST;   // [256 * tiles]
-    uint64_t *SELST;  // [Ecap / kSelTile + 1] decoupled look-back status
-    int *TICKETS;     // [n_epochs] dynamic tile tickets, one counter per compaction launch
+    int *SELCNT;      // [kSelBlocks] per-chunk match counts of the compaction
     int *CTR;         // [CTR_COUNT]
     const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
 };
@@ -63,7 +63,7 @@ void launch_init_box(const Bufs &b, int D, int Wd, const double *lo, const doubl
 void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int relu, int V, int K, int N,
                  const double *Wt, const double *bias, int Wd, int lw0, hipStream_t st);
 void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ecap_hint, hipStream_t st);
-void launch_select(const Bufs &b, uint16_t target, uint32_t epoch, int Emax, hipStream_t st);
+void launch_select(const Bufs &b, uint16_t target, hipStream_t st);
 void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st);
 void launch_sort(const Bufs &b, int n, hipStream_t st);  // result in K32a/VALa
 void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st);

@@ -240,96 +240,108 @@ void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ehint, 
 
 // ---------------------------------------------- step 3: splitting edges
 //
-// Ordered stream compaction of {e : NXT[e] == target} with a wave ballot /
-// prefix inside each tile and decoupled look-back between tiles (tiles are
-// taken from a ticket counter, so every predecessor of a waiting tile is
-// resident and will publish). Status words carry an epoch so that they never
-// need clearing: epoch << 34 | flag << 32 | count, flag 1 = tile aggregate,
-// 2 = inclusive prefix.
-__device__ __forceinline__ uint64_t sel_pack(uint32_t epoch, uint32_t flag, uint32_t v) {
-    return ((uint64_t)epoch << 34) | ((uint64_t)flag << 32) | v;
+// Ordered stream compaction of {e : NXT[e] == target}. The edge array is cut
+// into kSelBlocks contiguous chunks, one per workgroup. The first kernel counts
+// the matches of each chunk; the second re-reads its chunk, takes its offset
+// as the sum of the counts of the chunks before it, and writes the matching
+// ids in order (wave ballot / prefix sum inside each tile). No workgroup ever
+// waits on another, so the scan runs at streaming speed on all XCDs.
+__device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, int base, int E, uint16_t target) {
+    uint32_t hit = 0;
+    if (base + kSelItems <= E) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(nxt + base);
+        const uint4 a = p[0], c = p[1];
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if ((uint16_t)(w[i] & 0xFFFFu) == target) hit |= 1u << (2 * i);
+            if ((uint16_t)(w[i] >> 16) == target) hit |= 1u << (2 * i + 1);
+        }
+    } else {
+        for (int i = 0; i < kSelItems; ++i)
+            if (base + i < E && nxt[base + i] == target) hit |= 1u << i;
+    }
+    return hit;
 }
 
-__global__ __launch_bounds__(kThreads) void k_select(Bufs b, uint16_t target, uint32_t epoch) {
-    __shared__ int s_tile, s_prefix;
-    __shared__ int s_wsum[kThreads / 64];
+__device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
+    const int per = ((E + (int)gridDim.x - 1) / (int)gridDim.x + kSelItems - 1) / kSelItems * kSelItems;
+    c0 = min(E, (int)blockIdx.x * per);
+    c1 = min(E, c0 + per);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sel_count(Bufs b, uint16_t target) {
+    __shared__ int s_w[kThreads / 64];
     const int E = b.CTR[CTR_E];
-    const int ntiles = (E + kSelTile - 1) / kSelTile;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    int *tickets = b.TICKETS + epoch;
-    if (blockIdx.x == 0 && t == 0) b.CTR[CTR_KVALID] = 0;  // counted by the split that follows
-    if (ntiles == 0) {
-        if (blockIdx.x == 0 && t == 0) b.CTR[CTR_S] = 0;
-        return;
+    int c0, c1;
+    sel_chunk(E, c0, c1);
+    int cnt = 0;
+    for (int base = c0 + threadIdx.x * kSelItems; base < c1; base += kSelTile)
+        cnt += __popc(match16(b.NXT, base, c1, target));
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
+        b.SELCNT[blockIdx.x] = t;
     }
-    for (;;) {
-        if (t == 0) s_tile = atomicAdd(tickets, 1);
-        __syncthreads();
-        const int tile = s_tile;
-        if (tile >= ntiles) break;
-        const int base = tile * kSelTile + t * kSelItems;
-        uint32_t hit = 0;  // bit i set: edge base+i splits now
-#pragma unroll
-        for (int i = 0; i < kSelItems; ++i) {
-            const int e = base + i;
-            if (e < E && b.NXT[e] == target) hit |= 1u << i;
-        }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sel_scatter(Bufs b, uint16_t target) {
+    __shared__ int s_w[kThreads / 64];
+    __shared__ int s_base;
+    const int E = b.CTR[CTR_E];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int c0, c1;
+    sel_chunk(E, c0, c1);
+    // offset of this chunk: sum of the counts of the chunks before it
+    int pre = 0;
+    for (int i = t; i < (int)blockIdx.x; i += kThreads) pre += b.SELCNT[i];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if (lane == 0) s_w[wave] = pre;
+    __syncthreads();
+    if (t == 0) {
+        int x = 0;
+        for (int w = 0; w < kThreads / 64; ++w) x += s_w[w];
+        s_base = x;
+        if (blockIdx.x == gridDim.x - 1) b.CTR[CTR_S] = x + b.SELCNT[blockIdx.x];
+    }
+    __syncthreads();
+    int run = s_base;
+    for (int tb = c0; tb < c1; tb += kSelTile) {
+        const int base = tb + t * kSelItems;
+        uint32_t hit = base < c1 ? match16(b.NXT, base, c1, target) : 0u;
         const int cnt = __popc(hit);
-        // wave inclusive scan
         int incl = cnt;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(incl, o, 64);
             if (lane >= o) incl += y;
         }
-        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();  // s_w reuse
+        if (lane == 63) s_w[wave] = incl;
         __syncthreads();
         int wave_off = 0, total = 0;
 #pragma unroll
         for (int w = 0; w < kThreads / 64; ++w) {
-            const int ws = s_wsum[w];
+            const int ws = s_w[w];
             if (w < wave) wave_off += ws;
             total += ws;
         }
-        if (t == 0) {
-            uint64_t *st = b.SELST;
-            int prefix = 0;
-            if (tile == 0) {
-                __hip_atomic_store(&st[0], sel_pack(epoch, 2, (uint32_t)total), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(&st[tile], sel_pack(epoch, 1, (uint32_t)total), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                int p = tile - 1;
-                for (;;) {
-                    const uint64_t s = __hip_atomic_load(&st[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    const uint32_t ep = (uint32_t)(s >> 34), fl = (uint32_t)(s >> 32) & 3u;
-                    if (ep != epoch || fl == 0) continue;  // predecessor not published yet
-                    prefix += (int)(uint32_t)s;
-                    if (fl == 2) break;
-                    --p;
-                }
-                __hip_atomic_store(&st[tile], sel_pack(epoch, 2, (uint32_t)(prefix + total)), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-            s_prefix = prefix;
-            if (tile == ntiles - 1) b.CTR[CTR_S] = prefix + total;
-        }
-        __syncthreads();
-        int pos = s_prefix + wave_off + incl - cnt;
+        int pos = run + wave_off + incl - cnt;
         while (hit) {
             const int i = __builtin_ctz(hit);
             hit &= hit - 1;
             b.SPL[pos++] = base + i;
         }
-        __syncthreads();  // s_tile / s_wsum reuse
+        run += total;
     }
 }
 
-void launch_select(const Bufs &b, uint16_t target, uint32_t epoch, int Emax, hipStream_t st) {
-    int tiles = (Emax + kSelTile - 1) / kSelTile;
-    int grid = tiles < 1 ? 1 : (tiles > 2048 ? 2048 : tiles);
-    hipLaunchKernelGGL(k_select, dim3(grid), dim3(kThreads), 0, st, b, target, epoch);
+void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_count, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
+    hipLaunchKernelGGL(k_sel_scatter, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
 }
 
 // -------------------------------------------- steps 4-5a: split and keys
@@ -345,16 +357,21 @@ void launch_select(const Bufs &b, uint16_t target, uint32_t epoch, int Emax, hip
 // The splitting edge's sign-vector over earlier entries has D-1 zeros; each is
 // perturbed to + and - (box zeros only to +, Sec. 4.1) to give the parent
 // 2-faces, hashed as the sum of per-word hashes (Sec. 4.2.2).
-template <int G>
+//
+// Every load of a split (both endpoint rows of pre-activations, signs and
+// coordinates) is issued before any arithmetic or store, so a wave keeps
+// ~NC+3 independent memory requests in flight per split. Lane c of chunk k
+// holds column k*G + c; the sign words of the layer come straight from the
+// chunk ballots (no LDS).
+template <int G, int NC>
 __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, int E0, int S) {
-    extern __shared__ uint64_t lds_codes[];  // [groups][nw]
     constexpr int groups = kThreads / G;
-    const int nw = g.lw1 - g.lw0;
+    constexpr int wpc = G / 32;  // sign words per chunk
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
-    const int half = (threadIdx.x & 63) / G;  // group within the wave (G = 32: 0 or 1)
-    uint64_t *codes = lds_codes + (size_t)grp * nw;
-    const int D = g.D, Wd = g.Wd, ZS = g.ZS, j = g.j;
+    const int half = (threadIdx.x & 63) / G;  // G == 32: which half of the wave
+    const int D = g.D, Wd = g.Wd, ZS = g.ZS, j = g.j, N = g.Nl;
+    const int nw = g.lw1 - g.lw0;
     for (int s = blockIdx.x * groups + grp; s < S; s += gridDim.x * groups) {
         const int e = b.SPL[s];
         if ((unsigned)e >= (unsigned)E0) {
@@ -366,62 +383,76 @@ __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, 
             if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
             continue;
         }
-        const double za = b.Z[(size_t)ab.x * ZS + j], zb = b.Z[(size_t)ab.y * ZS + j];
+        const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;
+        const uint64_t *Ra = b.SG + (size_t)ab.x * Wd, *Rb = b.SG + (size_t)ab.y * Wd;
+        // ---- loads
+        const double za = Za[j], zb = Zb[j];
+        double A[NC], B[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int c = k * G + lane;
+            A[k] = c < N ? Za[c] : 0.0;
+            B[k] = c < N ? Zb[c] : 0.0;
+        }
+        const uint64_t wa0 = lane < Wd ? Ra[lane] : 0ull, wb0 = lane < Wd ? Rb[lane] : 0ull;
+        const double xa = lane < D ? b.X[(size_t)ab.x * D + lane] : 0.0;
+        const double xb = lane < D ? b.X[(size_t)ab.y * D + lane] : 0.0;
+        // ---- interpolation
         const bool apos = za > 0.0;
-        const int p = apos ? ab.x : ab.y, q = apos ? ab.y : ab.x;
         const double zp = apos ? za : zb, zq = apos ? zb : za;
         const double tt = zp / (zp - zq);
         const size_t x0 = (size_t)V0 + s;
-        for (int d = lane; d < D; d += G) {
-            const double xp = b.X[(size_t)p * D + d], xq = b.X[(size_t)q * D + d];
-            b.X[x0 * D + d] = xp + tt * (xq - xp);
-        }
         int bad = 0;
-        const double *Zp = b.Z + (size_t)p * ZS, *Zq = b.Z + (size_t)q * ZS;
-        double *Zx = b.Z + x0 * ZS;
-        for (int c0 = 0; c0 < g.Nl; c0 += G) {
-            const int c = c0 + lane;
-            const bool in = c < g.Nl;
-            double z = 0.0;
-            if (in) {
-                const double a = Zp[c], bq = Zq[c];
-                z = (c == j) ? 0.0 : a + tt * (bq - a);
-                Zx[c] = z;
-                if (c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
-            }
-            const uint64_t pb = __ballot(in && z > 0.0);
-            const uint64_t nb = __ballot(in && z < 0.0);
-            if (G == 64) {
-                if (lane == 0) codes[c0 >> 5] = codes_of((uint32_t)pb, (uint32_t)nb);
-                if (lane == 1 && (c0 >> 5) + 1 < nw) codes[(c0 >> 5) + 1] = codes_of((uint32_t)(pb >> 32), (uint32_t)(nb >> 32));
-            } else {
-                if (lane == 0) codes[c0 >> 5] = codes_of((uint32_t)(pb >> (32 * half)), (uint32_t)(nb >> (32 * half)));
-            }
+        double Zx[NC];
+        uint64_t pb[NC], nb[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int c = k * G + lane;
+            const bool in = c < N;
+            const double p = apos ? A[k] : B[k], q = apos ? B[k] : A[k];
+            const double z = (c == j) ? 0.0 : p + tt * (q - p);
+            if (in && c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
+            Zx[k] = z;
+            pb[k] = __ballot(in && z > 0.0);
+            nb[k] = __ballot(in && z < 0.0);
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        // sign row of x0, hash of the edge's sign-vector, zeros, next crossings
-        uint64_t hsum = 0;
-        int nz = 0, nkeys = 0;
-        int da = kNoCol, db = kNoCol;
-        const uint64_t *Rp = b.SG + (size_t)p * Wd, *Rq = b.SG + (size_t)q * Wd;
-        uint64_t *Rx = b.SG + x0 * Wd;
-        for (int w = lane; w < Wd; w += G) {
-            const uint64_t rp = Rp[w], rq = Rq[w];
+        const double xp = apos ? xa : xb, xq = apos ? xb : xa;
+        const double x0c = xp + tt * (xq - xp);
+        // ---- sign row of x0, hash of the edge's sign-vector, zeros, next crossings
+        uint64_t hsum = 0, rx0 = 0, f0 = 0;
+        int nz = 0, nkeys = 0, da = kNoCol, db = kNoCol;
+        for (int w = lane, it = 0; w < Wd; w += G, ++it) {
+            const uint64_t wa = it == 0 ? wa0 : Ra[w], wb = it == 0 ? wb0 : Rb[w];
             const uint64_t lt = lt_mask(w, g.wn, g.bn), gt = gt_mask(w, g.wn, g.bn, g.lw1);
-            const uint64_t f = (rp | rq) & lt;
+            const uint64_t f = (wa | wb) & lt;
             if (f & (f >> 1) & 0x5555555555555555ull) bad |= FLAG_CONFLICT;
-            const uint64_t cw = (w >= g.lw0 && w < g.lw1) ? codes[w - g.lw0] : 0ull;
+            uint64_t cw = 0;
+            const int u = w - g.lw0;
+            if (u >= 0 && u < nw) {
+                const int ku = u / wpc, sh = 32 * (wpc == 2 ? (u & 1) : half);
+                uint64_t P = 0, Q = 0;
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+                    if (k == ku) {
+                        P = pb[k];
+                        Q = nb[k];
+                    }
+                cw = codes_of((uint32_t)(P >> sh), (uint32_t)(Q >> sh));
+            }
             const uint64_t rx = f | (cw & gt);
-            Rx[w] = rx;
+            if (it == 0) {
+                rx0 = rx;
+                f0 = f;
+            } else {
+                b.SG[x0 * Wd + w] = rx;
+            }
             if (w <= g.wn) hsum += word_hash(w, f);
             const uint64_t zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
             const int zc = __popcll(zm);
             nz += zc;
             nkeys += (w == 0) ? zc : 2 * zc;  // box entries all live in word 0
-            const uint64_t ra = apos ? rp : rq, rb = apos ? rq : rp;
-            da = min(da, first_col((ra ^ rx) & gt, w, g.lw0));
-            db = min(db, first_col((rx ^ rb) & gt, w, g.lw0));
+            da = min(da, first_col((wa ^ rx) & gt, w, g.lw0));
+            db = min(db, first_col((rx ^ wb) & gt, w, g.lw0));
         }
         hsum = group_sum<G>(hsum);
         nz = group_sum<G>(nz);
@@ -429,14 +460,22 @@ __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, 
         da = group_min<G>(da);
         db = group_min<G>(db);
         bad = group_or<G>(bad);
+        // ---- stores
+        if (lane < D) b.X[x0 * D + lane] = x0c;
+        double *Zo = b.Z + x0 * ZS;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int c = k * G + lane;
+            if (c < N) Zo[c] = Zx[k];
+        }
+        if (lane < Wd) b.SG[x0 * Wd + lane] = rx0;
         if (lane == 0) {
-            if (nz != D - 1) bad |= FLAG_ZERO_COUNT;
+            if (nz != D - 1 || ktot > g.P) bad |= FLAG_ZERO_COUNT;
             if (bad) raise_flag(b.CTR, bad);
             b.EDG[e] = make_int2(ab.x, (int)x0);
             b.EDG[E0 + s] = make_int2((int)x0, ab.y);
             b.NXT[e] = da == kNoCol ? kNone : (uint16_t)da;
             b.NXT[E0 + s] = db == kNoCol ? kNone : (uint16_t)db;
-            if (ktot) atomicAdd(&b.CTR[CTR_KVALID], ktot);
         }
         if (g.P > 0) {
             // exclusive prefix of key counts over the group's lanes
@@ -448,29 +487,28 @@ __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, 
             }
             int r = incl - nkeys;
             const size_t sbase = (size_t)s * g.P;
-            for (int w = lane; w < Wd && nkeys; w += G) {
-                const uint64_t rp = Rp[w], rq = Rq[w];
+            for (int w = lane, it = 0; w < Wd && nkeys; w += G, ++it) {
                 const uint64_t lt = lt_mask(w, g.wn, g.bn);
-                const uint64_t f = (rp | rq) & lt;
+                const uint64_t f = it == 0 ? f0 : ((Ra[w] | Rb[w]) & lt);
                 uint64_t zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
+                if (!zm) continue;
                 const uint64_t hw = word_hash(w, f);
                 while (zm) {
                     const int bit = __builtin_ctzll(zm);
                     zm &= zm - 1;
                     for (int minus = 0; minus < (w == 0 ? 1 : 2); ++minus) {
-                        const uint64_t f2 = f | ((minus ? 2ull : 1ull) << bit);
-                        const uint64_t h = hsum - hw + word_hash(w, f2);
-                        const size_t slot = sbase + r++;
-                        if (r <= g.P) {
+                        const uint64_t h = hsum - hw + word_hash(w, f | ((minus ? 2ull : 1ull) << bit));
+                        if (r < g.P) {
+                            const size_t slot = sbase + r;
                             b.K32a[slot] = (uint32_t)(h >> 33);
                             b.FULL[slot] = h;
                             b.PINFO[slot] = ((uint32_t)w << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
                         }
+                        ++r;
                     }
                 }
             }
             for (int rr = ktot + lane; rr < g.P; rr += G) b.K32a[sbase + rr] = kSentinel;
-            if (ktot > g.P && lane == 0) raise_flag(b.CTR, FLAG_ZERO_COUNT);
         }
     }
 }
@@ -481,11 +519,14 @@ void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipSt
     const int groups = kThreads / G;
     int grid = (S + groups - 1) / groups;
     grid = grid > 16384 ? 16384 : grid;
-    const size_t lds = (size_t)groups * (g.lw1 - g.lw0) * sizeof(uint64_t);
-    if (G == 64)
-        hipLaunchKernelGGL(k_split<64>, dim3(grid), dim3(kThreads), lds, st, b, g, V0, E0, S);
+    if (G == 32)
+        hipLaunchKernelGGL((k_split<32, 1>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+    else if (g.Nl <= 64)
+        hipLaunchKernelGGL((k_split<64, 1>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+    else if (g.Nl <= 128)
+        hipLaunchKernelGGL((k_split<64, 2>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
     else
-        hipLaunchKernelGGL(k_split<32>, dim3(grid), dim3(kThreads), lds, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<64, 4>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
 }
 
 // ---------------------------------------------------- step 5b: radix sort
@@ -508,26 +549,41 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *__restri
     hist[(size_t)t * ntiles + tile] = h[t];
 }
 
+// exclusive scan of the [digit][tile] histogram in place: one workgroup of
+// 1024 threads, 4 consecutive counters per thread, coalesced 16-byte accesses
 __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, int len) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int chunk = (len + 1023) / 1024;
-    const int b0 = t * chunk, b1 = min(len, b0 + chunk);
-    uint32_t s = 0;
-    for (int i = b0; i < b1; ++i) s += hist[i];
-    part[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t y = t >= o ? part[t - o] : 0u;
+    __shared__ uint32_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < len; base += 4096) {
+        const int i0 = base + 4 * t;
+        uint32_t x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = i0 + k < len ? hist[i0 + k] : 0u;
+        const uint32_t tsum = x[0] + x[1] + x[2] + x[3];
+        uint32_t incl = tsum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
         __syncthreads();
-        part[t] += y;
+        uint32_t woff = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t v = wsum[w];
+            if (w < wave) woff += v;
+            total += v;
+        }
+        uint32_t run = carry + woff + incl - tsum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < len) hist[i0 + k] = run;
+            run += x[k];
+        }
+        carry += total;
         __syncthreads();
-    }
-    uint32_t run = part[t] - s;
-    for (int i = b0; i < b1; ++i) {
-        const uint32_t x = hist[i];
-        hist[i] = run;
-        run += x;
     }
 }
 
@@ -631,10 +687,14 @@ __device__ void emit_pair(const Bufs &b, const StepGeom &g, int V0, int nslots, 
 __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, int E1, int nslots) {
     const uint32_t *KS = b.K32a;
     const uint32_t *VS = b.VALa;
-    if (blockIdx.x == 0 && threadIdx.x == 0) b.CTR[CTR_E] = E1 + b.CTR[CTR_KVALID] / 2;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += gridDim.x * blockDim.x) {
         const uint32_t k = KS[i];
-        if (k == kSentinel) continue;
+        // valid keys (< 2^31) sort before the sentinels: the last valid one fixes the edge count
+        if (k == kSentinel) {
+            if (i == 0) b.CTR[CTR_E] = E1;
+            continue;
+        }
+        if (i + 1 == nslots || KS[i + 1] == kSentinel) b.CTR[CTR_E] = E1 + (i + 1) / 2;
         if (i > 0 && KS[i - 1] == k) continue;  // not the start of a run
         int j = i + 1;
         while (j < nslots && KS[j] == k) ++j;

@@ -25,7 +25,7 @@ KERNEL_FAMILIES = ["gemm", "next", "select", "split", "sort", "pair"]
 SYMBOLS = [
     "pcx_last_error", "pcx_mlp_create", "pcx_mlp_free", "pcx_extract", "pcx_complex_info",
     "pcx_complex_steps", "pcx_complex_copy", "pcx_complex_device", "pcx_complex_kernel_time",
-    "pcx_complex_free",
+    "pcx_complex_free", "pcx_cache_trim",
 ]
 
 
@@ -65,6 +65,8 @@ def _load():
     lib.pcx_complex_kernel_time.argtypes = [vp, i32, PD, C.POINTER(i64)]
     lib.pcx_complex_free.argtypes = [vp]
     lib.pcx_complex_free.restype = None
+    lib.pcx_cache_trim.argtypes = []
+    lib.pcx_cache_trim.restype = None
     for s in SYMBOLS:
         getattr(lib, s)
     return lib
@@ -76,6 +78,11 @@ _lib = _load()
 def _check(rc: int):
     if rc != PCX_OK:
         raise PcxError(rc, _lib.pcx_last_error().decode())
+
+
+def cache_trim() -> None:
+    """``pcx_cache_trim``: give cached device blocks back to the HIP runtime."""
+    _lib.pcx_cache_trim()
 
 
 def last_error() -> str:
@@ -209,14 +216,24 @@ class Complex:
         self.close()
 
 
-def extract(mlp: MLP, lo, hi, include_output: bool = False, timing: bool = False, stream=None,
+def timing_mask(families) -> int:
+    """Bitmask for ``extract(timing=...)`` from family names (or True for all)."""
+    if families is True:
+        return (1 << len(KERNEL_FAMILIES)) - 1
+    if not families:
+        return 0
+    return sum(1 << KERNEL_FAMILIES.index(f) for f in families)
+
+
+def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=None,
             max_bytes: int = 0) -> Complex:
     """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
-    o = _Opts(int(bool(include_output)), int(bool(timing)), 0, 0, int(max_bytes), stream)
+    tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
+    o = _Opts(int(bool(include_output)), int(tm), 0, 0, int(max_bytes), stream)
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))
