@@ -70,7 +70,8 @@ def algorithmic_cost(widths, steps, include_output=False):
             by["split"] += S * (4 + 8 + 3 * (8.0 * D + 8.0 * N + 8.0 * Wd) + 16 + 4) + 4.0 * S * P + 12.0 * Kv
             # sort: linear grouping reads and writes each (key, slot) pair once
             by["sort"] += 16.0 * S * P
-            # pair: sorted (key, slot), hash + entry per key; per pair two face rows, one edge, one crossing
+            # pair: per key its (key, slot) or table entry, hash and perturbed entry; per pair two face
+            # rows, one edge, one next crossing
             by["pair"] += Kv * (8.0 + 12.0) + (Kv / 2) * (2 * 8.0 * (wn + 1) + 8 + 2)
         s0 += N
     return by, flops
@@ -111,6 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain_large", help="workloads function name (default: the 768-neuron net)")
+    ap.add_argument("--pairing", default="hash", choices=["hash", "sort"], help="step-5 grouping of 2-face keys")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -129,7 +131,7 @@ def main():
     torch.cuda.synchronize()
 
     def run(timing):
-        cx = pcx.extract(mlp, box.lo, box.hi, include_output=incl, timing=timing)
+        cx = pcx.extract(mlp, box.lo, box.hi, include_output=incl, timing=timing, pairing=args.pairing)
         return cx
 
     # warm-up: sizes the buffers (capacity hints) and finds the dominant kernel family
@@ -193,7 +195,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain extraction, MLP {'-'.join(map(str, net.widths))} ReLU, "
                                f"He-normal weights, U(-0.5,0.5) biases, box [-1,1]^{D}",
-                   "neurons_subdivided": int(info.n_steps), "parallelism": "single GPU"},
+                   "neurons_subdivided": int(info.n_steps), "pairing": args.pairing,
+                   "parallelism": "single GPU"},
         "vertices_per_s": info.V / T,
         "edges_per_s": info.E / T,
         "V": info.V, "E": info.E, "splits": info.total_splits, "pairs": info.total_pairs,

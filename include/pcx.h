@@ -50,6 +50,9 @@ extern "C" {
 #define PCX_ERR_DEVICE (-4)     /* a HIP runtime call failed */
 #define PCX_ERR_CAPACITY (-5)   /* result would exceed pcx_opts.max_bytes */
 
+#define PCX_PAIR_HASH 0 /* open-addressing table on 64-bit 2-face hashes, linear time */
+#define PCX_PAIR_SORT 1 /* LSD radix sort of 31-bit 2-face keys (the paper's sort, Sec. 5.1) */
+
 typedef struct pcx_mlp pcx_mlp;
 typedef struct pcx_complex pcx_complex;
 
@@ -57,7 +60,7 @@ typedef struct pcx_complex pcx_complex;
 typedef struct {
     int32_t include_output; /* 1: subdivide the output neurons too (zero level set, Sec. 5.4) */
     int32_t timing;         /* bit f set: time kernel family f (PCX_K_*) with HIP events on the stream */
-    int32_t reserved0;
+    int32_t pairing;        /* step 5 grouping of 2-face keys: PCX_PAIR_HASH (default) or PCX_PAIR_SORT */
     int32_t reserved1;
     uint64_t max_bytes;     /* cap on device bytes the extraction may hold; 0 = no cap */
     void *stream;           /* hipStream_t to run on; NULL = the default stream */
@@ -114,8 +117,9 @@ int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void 
 #define PCX_K_NEXT 1     /* per-layer first-crossing scan of every edge (steps 2-3) */
 #define PCX_K_SELECT 2   /* per-step splitting-edge compaction (step 3) */
 #define PCX_K_SPLIT 3    /* per-step interpolation, split, 2-face keys (steps 4-5) */
-#define PCX_K_SORT 4     /* per-step radix sort of 2-face keys (step 5) */
-#define PCX_K_PAIR 5     /* per-step pairing into intersecting edges (step 5) */
+#define PCX_K_SORT 4     /* per-step radix sort of 2-face keys (step 5, PCX_PAIR_SORT) */
+#define PCX_K_PAIR 5     /* per-step pairing into intersecting edges (step 5; with PCX_PAIR_HASH the
+                            table inserts run inside PCX_K_SPLIT) */
 #define PCX_K_COUNT 6
 #define PCX_K_ALL ((1 << PCX_K_COUNT) - 1)
 int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, int64_t *launches);

@@ -200,6 +200,11 @@ struct Extraction {
     Arena arena;
     Bufs b{};
     size_t Vcap = 0, Ecap = 0, Scap = 0, Kcap = 0, Hcap = 0;
+    int pair_mode = PAIR_HASH;
+    HEntry *HT[2] = {nullptr, nullptr};  // 2-face hash tables, alternating by step
+    size_t Tcap = 0;                     // entries per table
+    uint32_t Tused[2] = {0, 0};          // entries a step left to clear
+    int hparity = 0;
     int D = 0, Wd = 0, ZS = 0, P = 0;
     int *hctr = nullptr;  // pinned
     EventPool ev;
@@ -294,13 +299,28 @@ struct Extraction {
         if (S > Scap) return fail(PCX_ERR_DEVICE, "split list smaller than the split count");
         if (K > Kcap) {
             size_t nc = std::max(K, Kcap * 2);
-            if ((rc = grow_scratch(b.K32a, Kcap, nc))) return rc;
-            if ((rc = grow_scratch(b.K32b, Kcap, nc))) return rc;
-            if ((rc = grow_scratch(b.VALa, Kcap, nc))) return rc;
-            if ((rc = grow_scratch(b.VALb, Kcap, nc))) return rc;
+            if (pair_mode == PAIR_SORT) {
+                if ((rc = grow_scratch(b.K32a, Kcap, nc))) return rc;
+                if ((rc = grow_scratch(b.K32b, Kcap, nc))) return rc;
+                if ((rc = grow_scratch(b.VALa, Kcap, nc))) return rc;
+                if ((rc = grow_scratch(b.VALb, Kcap, nc))) return rc;
+            }
             if ((rc = grow_scratch(b.FULL, Kcap, nc))) return rc;
             if ((rc = grow_scratch(b.PINFO, Kcap, nc))) return rc;
             Kcap = nc;
+        }
+        if (pair_mode == PAIR_HASH) {
+            size_t tc = 256;
+            while (tc < 2 * Kcap) tc <<= 1;
+            if (tc > Tcap) {
+                for (int t = 0; t < 2; ++t) {
+                    if ((rc = grow_scratch(HT[t], Tcap, tc))) return rc;
+                    HIPCHK(hipMemsetAsync(HT[t], 0, tc * sizeof(HEntry), st));
+                    Tused[t] = 0;
+                }
+                Tcap = tc;
+            }
+            return PCX_OK;
         }
         size_t h = (size_t)kSortBins * ((K + kSortTile - 1) / kSortTile + 1);
         if (h > Hcap) {
@@ -411,6 +431,8 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     x.Wd = Wd;
     x.ZS = ZS;
     x.P = D >= 2 ? 2 * (D - 1) : 0;
+    if (o.pairing != PCX_PAIR_HASH && o.pairing != PCX_PAIR_SORT) return fail(PCX_ERR_INVALID, "unknown pairing");
+    x.pair_mode = o.pairing == PCX_PAIR_SORT ? PAIR_SORT : PAIR_HASH;
     hipStream_t st = x.st;
     int rc;
 
@@ -523,11 +545,29 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
             g.wn = lw[l] + (j >> 5);
             g.bn = 2 * (j & 31);
             g.P = x.P;
+            g.pair_mode = x.pair_mode;
+            g.HT = nullptr;
+            g.hmask = 0;
+            uint32_t tsz = 256;
+            if (x.P > 0 && x.pair_mode == PAIR_HASH) {
+                while (tsz < 2 * (uint64_t)S * x.P) tsz <<= 1;
+                g.HT = x.HT[x.hparity];
+                g.hmask = tsz - 1;
+            }
             if ((rc = x.mark(PCX_K_SPLIT, true))) return rc;
             launch_split(x.b, g, (int)V, (int)E, (int)S, st);
             if ((rc = x.mark(PCX_K_SPLIT, false))) return rc;
             HIPCHK(hipGetLastError());
-            if (x.P > 0) {
+            if (x.P > 0 && x.pair_mode == PAIR_HASH) {
+                if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
+                const int other = x.hparity ^ 1;
+                launch_hash_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), x.HT[other], x.Tused[other], st);
+                if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
+                HIPCHK(hipGetLastError());
+                x.Tused[other] = 0;
+                x.Tused[x.hparity] = tsz;
+                x.hparity = other;
+            } else if (x.P > 0) {
                 if ((rc = x.mark(PCX_K_SORT, true))) return rc;
                 launch_sort(x.b, (int)(S * x.P), st);
                 if ((rc = x.mark(PCX_K_SORT, false))) return rc;

@@ -32,6 +32,16 @@ enum : int {
     FLAG_BOUNDS = 32,     // an index outside the live arrays (internal error; the access is skipped)
 };
 
+// One slot of the 2-face hash table; all-zero = empty. a, b = 1 + the key
+// slots of the first and second splitting edge that reached this 2-face.
+struct HEntry {
+    unsigned long long key;
+    uint32_t a, b;
+};
+constexpr int kPairItems = 4;  // key slots per thread in the hash pairing passes
+
+enum { PAIR_HASH = 0, PAIR_SORT = 1 };
+
 // Geometry of one neuron step (layer l, neuron j of that layer).
 struct StepGeom {
     int D, Wd, ZS;   // input dim, words per sign row, pre-activation row stride
@@ -40,6 +50,9 @@ struct StepGeom {
     int j;           // neuron within the layer
     int wn, bn;      // word and bit offset of this neuron's entry
     int P;           // 2-face key slots per split: 2(D-1)
+    int pair_mode;   // PAIR_HASH or PAIR_SORT
+    uint32_t hmask;  // hash table slots - 1 (PAIR_HASH)
+    HEntry *HT;      // this step's hash table (PAIR_HASH)
 };
 
 struct Bufs {
@@ -53,7 +66,7 @@ struct Bufs {
     uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot
     uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus
     uint32_t *HIST;   // [256 * tiles]
-    int *SELCNT;      // [kSelBlocks] per-chunk match counts of the compaction
+    int *SELCNT;      // [kSelBlocks] per-chunk match counts of the compaction (also the pairing passes)
     int *CTR;         // [CTR_COUNT]
     const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
 };
@@ -67,5 +80,9 @@ void launch_select(const Bufs &b, uint16_t target, hipStream_t st);
 void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st);
 void launch_sort(const Bufs &b, int n, hipStream_t st);  // result in K32a/VALa
 void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st);
+// hash pairing: count + ordered emit over the key slots; the emit also clears
+// `clear_n` entries of the table used by the previous step
+void launch_hash_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, HEntry *clear_t,
+                      uint32_t clear_n, hipStream_t st);
 
 }  // namespace pcx

@@ -344,6 +344,41 @@ void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
     hipLaunchKernelGGL(k_sel_scatter, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
 }
 
+// ----------------------------------------------- 2-face hash table (f1)
+//
+// Open addressing with linear probing on the full 64-bit key. The first
+// splitting edge to reach a 2-face claims the slot with a 64-bit CAS and
+// records its key slot in `a`; the second finds the key and records itself in
+// `b`. A third arrival means the 2-face is not met by exactly two splitting
+// edges (Sec. 4.2.2) and raises FLAG_RUN.
+__device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H, uint32_t u, int *ctr) {
+    uint32_t h = (uint32_t)H & mask;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const unsigned long long prev = atomicCAS(&T[h].key, 0ull, (unsigned long long)H);
+        if (prev == 0ull) {
+            T[h].a = u + 1;
+            return;
+        }
+        if (prev == (unsigned long long)H) {
+            if (atomicCAS(&T[h].b, 0u, u + 1) != 0u) raise_flag(ctr, FLAG_RUN);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+    raise_flag(ctr, FLAG_BOUNDS);  // table full: cannot happen at load factor <= 1/2
+}
+
+__device__ __forceinline__ int hash_find(const HEntry *T, uint32_t mask, uint64_t H) {
+    uint32_t h = (uint32_t)H & mask;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const unsigned long long k = T[h].key;
+        if (k == (unsigned long long)H) return (int)h;
+        if (k == 0ull) return -1;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
 // -------------------------------------------- steps 4-5a: split and keys
 //
 // One group of G lanes per splitting edge (p, q), p = V+ and q = V-:
@@ -500,15 +535,24 @@ __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, 
                         const uint64_t h = hsum - hw + word_hash(w, f | ((minus ? 2ull : 1ull) << bit));
                         if (r < g.P) {
                             const size_t slot = sbase + r;
-                            b.K32a[slot] = (uint32_t)(h >> 33);
-                            b.FULL[slot] = h;
                             b.PINFO[slot] = ((uint32_t)w << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
+                            if (g.pair_mode == PAIR_SORT) {
+                                b.K32a[slot] = (uint32_t)(h >> 33);
+                                b.FULL[slot] = h;
+                            } else {
+                                const uint64_t hk = h | (1ull << 63);  // never 0 (= empty)
+                                b.FULL[slot] = hk;
+                                hash_insert(g.HT, g.hmask, hk, (uint32_t)slot, b.CTR);
+                            }
                         }
                         ++r;
                     }
                 }
             }
-            for (int rr = ktot + lane; rr < g.P; rr += G) b.K32a[sbase + rr] = kSentinel;
+            for (int rr = ktot + lane; rr < g.P; rr += G) {
+                if (g.pair_mode == PAIR_SORT) b.K32a[sbase + rr] = kSentinel;
+                else b.FULL[sbase + rr] = 0ull;
+            }
         }
     }
 }
@@ -733,6 +777,126 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, h
     int grid = (nslots + kThreads - 1) / kThreads;
     grid = grid < 1 ? 1 : (grid > 8192 ? 8192 : grid);
     hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kThreads), 0, st, b, g, V0, E1, nslots);
+}
+
+// ---------------------------------- step 5c with the hash table (f1)
+//
+// Every valid key slot u finds its 2-face entry; the smaller of the two slots
+// owns the pair. Owners are emitted in slot order (chunk counts, then an
+// ordered scatter, as in the compaction), so the edge list is deterministic.
+__device__ __forceinline__ bool hash_owner(const Bufs &b, const StepGeom &g, int u, int nslots, int &partner) {
+    const uint64_t H = b.FULL[u];
+    if (H == 0ull) return false;
+    const int h = hash_find(g.HT, g.hmask, H);
+    if (h < 0) {
+        raise_flag(b.CTR, FLAG_BOUNDS);
+        return false;
+    }
+    const uint32_t a = g.HT[h].a, c = g.HT[h].b;
+    if (c == 0u || a == 0u) {
+        raise_flag(b.CTR, FLAG_RUN);
+        return false;
+    }
+    const uint32_t p = (a - 1 == (uint32_t)u) ? c - 1 : a - 1;
+    if (p >= (uint32_t)nslots) {
+        raise_flag(b.CTR, FLAG_BOUNDS);
+        return false;
+    }
+    partner = (int)p;
+    return (uint32_t)u < p;
+}
+
+__device__ __forceinline__ void pair_chunk(int n, int &c0, int &c1) {
+    const int per = ((n + (int)gridDim.x - 1) / (int)gridDim.x + kPairItems - 1) / kPairItems * kPairItems;
+    c0 = min(n, (int)blockIdx.x * per);
+    c1 = min(n, c0 + per);
+}
+
+__global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g, int nslots) {
+    __shared__ int s_w[kThreads / 64];
+    int c0, c1;
+    pair_chunk(nslots, c0, c1);
+    int cnt = 0;
+    for (int base = c0 + threadIdx.x * kPairItems; base < c1; base += kThreads * kPairItems)
+        for (int i = 0; i < kPairItems; ++i) {
+            int partner;
+            if (base + i < c1 && hash_owner(b, g, base + i, nslots, partner)) ++cnt;
+        }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
+        b.SELCNT[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int V0, int E1, int nslots,
+                                                          HEntry *clear_t, uint32_t clear_n) {
+    __shared__ int s_w[kThreads / 64];
+    __shared__ int s_base;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // the table of the previous step is no longer read: make it empty again
+    for (uint32_t i = blockIdx.x * kThreads + t; i < clear_n; i += gridDim.x * kThreads) {
+        HEntry z;
+        z.key = 0ull;
+        z.a = 0u;
+        z.b = 0u;
+        clear_t[i] = z;
+    }
+    int c0, c1;
+    pair_chunk(nslots, c0, c1);
+    int pre = 0;
+    for (int i = t; i < (int)blockIdx.x; i += kThreads) pre += b.SELCNT[i];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if (lane == 0) s_w[wave] = pre;
+    __syncthreads();
+    if (t == 0) {
+        int x = 0;
+        for (int w = 0; w < kThreads / 64; ++w) x += s_w[w];
+        s_base = x;
+        if (blockIdx.x == gridDim.x - 1) b.CTR[CTR_E] = E1 + x + b.SELCNT[blockIdx.x];
+    }
+    __syncthreads();
+    int run = s_base;
+    for (int tb = c0; tb < c1; tb += kThreads * kPairItems) {
+        const int base = tb + t * kPairItems;
+        int partner[kPairItems];
+        uint32_t own = 0;
+#pragma unroll
+        for (int i = 0; i < kPairItems; ++i)
+            if (base + i < c1 && hash_owner(b, g, base + i, nslots, partner[i])) own |= 1u << i;
+        const int cnt = __popc(own);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        __syncthreads();
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        int wave_off = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const int ws = s_w[w];
+            if (w < wave) wave_off += ws;
+            total += ws;
+        }
+        int pos = run + wave_off + incl - cnt;
+#pragma unroll
+        for (int i = 0; i < kPairItems; ++i)
+            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++);
+        run += total;
+    }
+}
+
+void launch_hash_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, HEntry *clear_t,
+                      uint32_t clear_n, hipStream_t st) {
+    hipLaunchKernelGGL(k_hpair_count, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g, nslots);
+    hipLaunchKernelGGL(k_hpair_emit, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g, V0, E1, nslots, clear_t,
+                       clear_n);
 }
 
 }  // namespace pcx

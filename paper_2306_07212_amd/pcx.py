@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpcx.so")
 PCX_OK, PCX_PENDING = 0, 1
 PCX_ERR_INVALID, PCX_ERR_OOM, PCX_ERR_DEGENERATE, PCX_ERR_DEVICE, PCX_ERR_CAPACITY = -1, -2, -3, -4, -5
 KERNEL_FAMILIES = ["gemm", "next", "select", "split", "sort", "pair"]
+PAIRING = {"hash": 0, "sort": 1}
 
 # every symbol include/pcx.h declares
 SYMBOLS = [
@@ -36,7 +37,7 @@ class PcxError(RuntimeError):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("pairing", C.c_int32),
                 ("reserved1", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p)]
 
 
@@ -226,14 +227,14 @@ def timing_mask(families) -> int:
 
 
 def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=None,
-            max_bytes: int = 0) -> Complex:
+            max_bytes: int = 0, pairing: str = "hash") -> Complex:
     """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
     tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
-    o = _Opts(int(bool(include_output)), int(tm), 0, 0, int(max_bytes), stream)
+    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], 0, int(max_bytes), stream)
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))

@@ -35,8 +35,8 @@ def gpu_complex(pcx, net, box, include_output=False, **kw):
     return X, S, Ed, steps, info
 
 
-def _compare(oracle_lib, pcx, net, box, incl=False, invariants=True):
-    X, S, Ed, steps, info = gpu_complex(pcx, net, box, incl)
+def _compare(oracle_lib, pcx, net, box, incl=False, invariants=True, pairing="hash"):
+    X, S, Ed, steps, info = gpu_complex(pcx, net, box, incl, pairing=pairing)
     r = oracle_lib.extract(net, box.lo, box.hi, include_output=incl)
     assert info.V == r.V and info.E == r.E
     assert np.array_equal(steps, r.steps), "per-step counters differ"
@@ -66,9 +66,10 @@ def test_plain_small_matches_oracle_and_golden(oracle_lib, pcx):
     ([3, 64, 1], 108, True),
     ([2, 1, 1, 1], 109, False),       # width-1 layers
 ])
-def test_small_nets_match_oracle(oracle_lib, pcx, widths, seed, incl):
+@pytest.mark.parametrize("pairing", ["hash", "sort"])
+def test_small_nets_match_oracle(oracle_lib, pcx, widths, seed, incl, pairing):
     net = wl.he_mlp(widths, seed)
-    _compare(oracle_lib, pcx, net, wl.cube(widths[0]), incl)
+    _compare(oracle_lib, pcx, net, wl.cube(widths[0]), incl, pairing=pairing)
 
 
 def test_asymmetric_box(oracle_lib, pcx):
@@ -84,11 +85,12 @@ def test_differentiable_small_matches_golden(oracle_lib, pcx):
     assert digest(S, Ed) == g["digest"]
 
 
-def test_differentiable_workload_matches_oracle(oracle_lib, pcx):
+@pytest.mark.parametrize("pairing", ["hash", "sort"])
+def test_differentiable_workload_matches_oracle(oracle_lib, pcx, pairing):
     """3 -> 64 -> 64 -> 64 -> 1 with the output's zero level set: ~0.67M vertices."""
     net = wl.differentiable()
     box = wl.cube(3)
-    X, S, Ed, steps, info = gpu_complex(pcx, net, box, True)
+    X, S, Ed, steps, info = gpu_complex(pcx, net, box, True, pairing=pairing)
     g = json.load(open(os.path.join(GOLDEN, "differentiable.json")))
     assert (info.V, info.E) == (g["V"], g["E"])
     assert np.array_equal(steps, np.array(g["steps"]))
@@ -97,11 +99,12 @@ def test_differentiable_workload_matches_oracle(oracle_lib, pcx):
     assert_same_complex((X, S, Ed), (r.X, r.S, r.edges), coord_tol=1e-10)
 
 
-def test_run_twice_bit_identical(pcx):
+@pytest.mark.parametrize("pairing", ["hash", "sort"])
+def test_run_twice_bit_identical(pcx, pairing):
     net = wl.he_mlp([3, 32, 32, 1], 121)
     box = wl.cube(3)
-    a = gpu_complex(pcx, net, box)
-    b = gpu_complex(pcx, net, box)
+    a = gpu_complex(pcx, net, box, pairing=pairing)
+    b = gpu_complex(pcx, net, box, pairing=pairing)
     for u, v in zip(a[:4], b[:4]):
         assert np.array_equal(u, v)
 
