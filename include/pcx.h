@@ -61,7 +61,8 @@ typedef struct {
     int32_t include_output; /* 1: subdivide the output neurons too (zero level set, Sec. 5.4) */
     int32_t timing;         /* bit f set: time kernel family f (PCX_K_*) with HIP events on the stream */
     int32_t pairing;        /* step 5 grouping of 2-face keys: PCX_PAIR_HASH (default) or PCX_PAIR_SORT */
-    int32_t reserved1;
+    int32_t record_tape;    /* 1: keep what pcx_backward needs (parents of new vertices, every layer's
+                               pre-activations); costs V * N_l doubles per subdivided layer */
     uint64_t max_bytes;     /* cap on device bytes the extraction may hold; 0 = no cap */
     void *stream;           /* hipStream_t to run on; NULL = the default stream */
 } pcx_opts;
@@ -106,6 +107,10 @@ int pcx_complex_steps(const pcx_complex *cx, int64_t *steps);
  * coords V*D doubles, signs V*Wd uint64 (packing above), edges E*2 int32. */
 int pcx_complex_copy(const pcx_complex *cx, double *coords, uint64_t *signs, int32_t *edges);
 
+/* The same copy into caller-allocated device buffers (any may be NULL), e.g.
+ * the storage of framework tensors; ordered on `stream` (NULL = default). */
+int pcx_complex_copy_device(const pcx_complex *cx, double *coords, uint64_t *signs, int32_t *edges, void *stream);
+
 /* Borrowed device pointers to the same three arrays, valid until
  * pcx_complex_free. Any out-pointer may be NULL. */
 int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void **edges);
@@ -125,6 +130,22 @@ int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void 
 int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, int64_t *launches);
 
 void pcx_complex_free(pcx_complex *cx);
+
+/* Gradient of a loss L(coordinates) with respect to every weight and bias,
+ * through the vertex positions (Sec. 5.3: a loss on the extracted complex is
+ * optimised through its vertices). cx must come from pcx_extract of the same
+ * mlp with opts.record_tape = 1. grad_coords: device, V*D doubles, dL/dx for
+ * every vertex in the complex's order. gW[l], gb[l]: device buffers of
+ * N_{l+1} x N_l and N_{l+1} doubles for l = 0 .. n_layers-1, overwritten
+ * (layers whose neurons were not subdivided get zeros). precision selects the
+ * arithmetic of the reverse pass: PCX_F64 or PCX_F32 (results still FP64).
+ * Each new vertex x0 = x_p + t (x_q - x_p), t = z_p / (z_p - z_q) of its
+ * splitting edge (Sec. 4.2.1) is differentiated exactly as the forward pass
+ * computed it; the call returns when the gradients are complete. */
+#define PCX_F64 0
+#define PCX_F32 1
+int pcx_backward(const pcx_mlp *mlp, const pcx_complex *cx, const double *grad_coords, double *const *gW,
+                 double *const *gb, int32_t precision, void *stream);
 
 /* Device blocks of finished extractions (scratch and freed complexes) are kept
  * by the library for reuse by later extractions on the same device. This call

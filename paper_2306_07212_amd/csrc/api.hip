@@ -42,6 +42,7 @@ struct pcx_mlp {
     int L = 0, D = 0;
     std::vector<int> widths;
     std::vector<double *> Wt;  // device, layer l: [N_{l-1}][N_l] (transposed for coalesced GEMM reads)
+    std::vector<double *> Wr;  // device, layer l: [N_l][N_{l-1}] as given (backward pass)
     std::vector<double *> b;   // device, [N_l]
     std::atomic<int64_t> hintV{0}, hintE{0};  // sizes seen by the last extraction (capacity hint)
 };
@@ -58,6 +59,13 @@ struct pcx_complex {
     double time_ms = 0.0;
     double ktime[PCX_K_COUNT] = {};
     int64_t klaunch[PCX_K_COUNT] = {};
+    // tape (record_tape): parents of each new vertex, each subdivided layer's
+    // pre-activation rows at its end (stride ZS), and the first step of each layer
+    bool taped = false;
+    int ZS = 0, nsub = 0;
+    int2 *PQ = nullptr;
+    std::vector<double *> Zl;
+    std::vector<int> layer_step0;
 };
 
 namespace {
@@ -76,18 +84,23 @@ struct Pool {
         const size_t g = bytes >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
         return (bytes + g - 1) / g * g;
     }
-    void *get(size_t bytes, size_t *got) {
+    // limit: largest block the caller may take (a cached block can be bigger than asked)
+    void *get(size_t bytes, size_t *got, size_t limit) {
         int dev = 0;
         (void)hipGetDevice(&dev);
         const size_t sz = size_class(bytes);
         *got = sz;
         {
+            // best fit among cached blocks of this device no larger than 1.6x the request
             std::lock_guard<std::mutex> lk(m);
-            auto it = cached.find({dev, sz});
-            if (it != cached.end() && !it->second.empty()) {
+            auto it = cached.lower_bound({dev, sz});
+            const size_t fit = std::min(limit, sz + sz / 2 + sz / 10);
+            for (; it != cached.end() && it->first.first == dev && it->first.second <= fit; ++it) {
+                if (it->second.empty()) continue;
                 void *p = it->second.back();
                 it->second.pop_back();
-                cached_bytes -= sz;
+                cached_bytes -= it->first.second;
+                *got = it->first.second;
                 return p;
             }
         }
@@ -144,7 +157,7 @@ struct Arena {
         if (cap && cur + sz > cap)
             return fail(PCX_ERR_CAPACITY, "extraction needs more device memory than max_bytes allows");
         size_t got = 0;
-        *p = pool().get(bytes, &got);
+        *p = pool().get(bytes, &got, cap ? (size_t)(cap - cur) : ~(size_t)0);
         if (!*p) return fail(PCX_ERR_OOM, "hipMalloc of " + std::to_string(sz) + " bytes failed");
         live.push_back({*p, got});
         cur += got;
@@ -205,6 +218,7 @@ struct Extraction {
     size_t Tcap = 0;                     // entries per table
     uint32_t Tused[2] = {0, 0};          // entries a step left to clear
     int hparity = 0;
+    bool tape = false;
     int D = 0, Wd = 0, ZS = 0, P = 0;
     int *hctr = nullptr;  // pinned
     EventPool ev;
@@ -274,6 +288,11 @@ struct Extraction {
         if ((rc = grow_keep(b.X, c0, need, used, (size_t)D))) return rc;
         if ((rc = grow_keep(b.SG, c1, need, used, (size_t)Wd))) return rc;
         if ((rc = grow_keep(b.Z, c2, need, used, (size_t)ZS))) return rc;
+        if (tape) {
+            size_t c3 = Vcap;
+            if ((rc = grow_keep(b.PQ, c3, need, used, 1))) return rc;
+            c2 = std::min(c2, c3);
+        }
         Vcap = std::min(c0, std::min(c1, c2));
         return PCX_OK;
     }
@@ -381,7 +400,15 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
         }
         m->Wt.push_back(dw);
         m->b.push_back(db);
+        double *dr = nullptr;
+        if (hipMalloc((void **)&dr, tmp.size() * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            pcx_mlp_free(m);
+            return fail(PCX_ERR_OOM, "hipMalloc for weights failed");
+        }
+        m->Wr.push_back(dr);
         if (hipMemcpy(dw, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dr, W[l], tmp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(db, b[l], (size_t)nout * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
             pcx_mlp_free(m);
             return fail(PCX_ERR_DEVICE, "copying weights to the device failed");
@@ -394,6 +421,7 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
 void pcx_mlp_free(pcx_mlp *m) {
     if (!m) return;
     for (auto p : m->Wt) (void)hipFree(p);
+    for (auto p : m->Wr) (void)hipFree(p);
     for (auto p : m->b) (void)hipFree(p);
     delete m;
 }
@@ -433,6 +461,8 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     x.P = D >= 2 ? 2 * (D - 1) : 0;
     if (o.pairing != PCX_PAIR_HASH && o.pairing != PCX_PAIR_SORT) return fail(PCX_ERR_INVALID, "unknown pairing");
     x.pair_mode = o.pairing == PCX_PAIR_SORT ? PAIR_SORT : PAIR_HASH;
+    x.tape = o.record_tape != 0;
+    std::vector<double *> tapeZ;
     hipStream_t st = x.st;
     int rc;
 
@@ -501,10 +531,19 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
         }
         // step 1 for the whole layer: pre-activations at every vertex
         if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
-        if (l == 0)
+        if (l == 0) {
             launch_gemm(x.b, ZS, x.b.X, D, 0, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
-        else
+        } else if (x.tape) {
+            // keep the previous layer's rows: evaluate into a fresh buffer
+            double *prev = x.b.Z;
+            void *q;
+            if ((rc = x.arena.alloc(&q, x.Vcap * (size_t)ZS * sizeof(double)))) return rc;
+            tapeZ.push_back(prev);
+            x.b.Z = (double *)q;
+            launch_gemm(x.b, ZS, prev, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+        } else {
             launch_gemm(x.b, ZS, x.b.Z, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+        }
         if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
         if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
         launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, st);
@@ -608,6 +647,21 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     x.arena.forget(x.b.X);
     x.arena.forget(x.b.SG);
     x.arena.forget(x.b.EDG);
+    if (x.tape) {
+        tapeZ.push_back(x.b.Z);
+        for (double *z : tapeZ) x.arena.forget(z);
+        x.arena.forget(x.b.PQ);
+        cx->taped = true;
+        cx->PQ = x.b.PQ;
+        cx->Zl = tapeZ;
+        int s0 = 0;
+        for (int l = 0; l < nsub; ++l) {
+            cx->layer_step0.push_back(s0);
+            s0 += mlp->widths[l + 1];
+        }
+    }
+    cx->ZS = ZS;
+    cx->nsub = nsub;
     cx->steps = std::move(steps);
     cx->total_splits = total_splits;
     int64_t pairs = 0;
@@ -675,7 +729,96 @@ void pcx_complex_free(pcx_complex *cx) {
     pool().put(cx->X);
     pool().put(cx->SG);
     pool().put(cx->EDG);
+    pool().put(cx->PQ);
+    for (double *z : cx->Zl) pool().put(z);
     delete cx;
+}
+
+int pcx_complex_copy_device(const pcx_complex *cx, double *coords, uint64_t *signs, int32_t *edges, void *stream) {
+    if (!cx) return fail(PCX_ERR_INVALID, "NULL complex");
+    hipStream_t st = (hipStream_t)stream;
+    if (coords)
+        HIPCHK(hipMemcpyAsync(coords, cx->X, (size_t)cx->V * cx->D * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (signs)
+        HIPCHK(hipMemcpyAsync(signs, cx->SG, (size_t)cx->V * cx->Wd * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    if (edges)
+        HIPCHK(hipMemcpyAsync(edges, cx->EDG, (size_t)cx->E * 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PCX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+int backward_impl(const pcx_mlp *mlp, const pcx_complex *cx, const double *grad, double *const *gW, double *const *gb,
+                  hipStream_t st) {
+    const int D = cx->D, ZS = cx->ZS, nsub = cx->nsub;
+    Arena ar;
+    int rc;
+    void *p;
+    int *dflag;
+    if ((rc = ar.alloc(&p, sizeof(int)))) return rc;
+    dflag = (int *)p;
+    HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), st));
+    if ((rc = ar.alloc(&p, (size_t)cx->V * D * sizeof(T)))) return rc;
+    T *gx = (T *)p;
+    if ((rc = ar.alloc(&p, (size_t)cx->V * ZS * sizeof(T)))) return rc;
+    T *gz = (T *)p;
+    bwd_init<T>(grad, gx, (size_t)cx->V * D, gz, (size_t)cx->V * ZS, st);
+    // layers that were not subdivided do not move any vertex
+    for (int l = nsub; l < mlp->L; ++l) {
+        HIPCHK(hipMemsetAsync(gW[l], 0, (size_t)mlp->widths[l + 1] * mlp->widths[l] * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(gb[l], 0, (size_t)mlp->widths[l + 1] * sizeof(double), st));
+    }
+    for (int l = nsub - 1; l >= 0; --l) {
+        const int N = mlp->widths[l + 1], K = mlp->widths[l];
+        const int s0 = cx->layer_step0[l];
+        for (int j = N - 1; j >= 0; --j) {
+            const int64_t *st4 = &cx->steps[(size_t)(s0 + j) * 4];
+            bwd_step<T>(cx->X, cx->Zl[l], cx->PQ, gx, gz, D, N, ZS, j, (int)st4[0], (int)st4[2], dflag, st);
+        }
+        HIPCHK(hipGetLastError());
+        const int Vs = (int)cx->steps[(size_t)s0 * 4];
+        const int chunks = std::max(1, std::min(256, Vs / 2048));
+        if ((rc = ar.alloc(&p, (size_t)chunks * N * (K + 1) * sizeof(double)))) return rc;
+        double *part = (double *)p;
+        T *gzp = nullptr;
+        if (l > 0) {
+            if ((rc = ar.alloc(&p, (size_t)Vs * ZS * sizeof(T)))) return rc;
+            gzp = (T *)p;
+        }
+        const double *hin = l == 0 ? cx->X : cx->Zl[l - 1];
+        bwd_layer<T>(gz, ZS, hin, l == 0 ? D : ZS, l > 0 ? 1 : 0, Vs, N, K, mlp->Wr[l], part, chunks, gW[l], gb[l],
+                     gzp, ZS, st);
+        HIPCHK(hipGetLastError());
+        if (gzp) {
+            HIPCHK(hipStreamSynchronize(st));
+            ar.release(gz);
+            gz = gzp;
+        }
+    }
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hflag) return fail(PCX_ERR_DEVICE, "internal error: tape index out of range");
+    return PCX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pcx_backward(const pcx_mlp *mlp, const pcx_complex *cx, const double *grad_coords, double *const *gW,
+                 double *const *gb, int32_t precision, void *stream) {
+    if (!mlp || !cx || !grad_coords || !gW || !gb) return fail(PCX_ERR_INVALID, "NULL argument");
+    if (!cx->taped) return fail(PCX_ERR_INVALID, "complex was extracted without record_tape");
+    if (cx->D != mlp->D || cx->nsub > mlp->L) return fail(PCX_ERR_INVALID, "complex does not belong to this network");
+    for (int l = 0; l < mlp->L; ++l)
+        if (!gW[l] || !gb[l]) return fail(PCX_ERR_INVALID, "NULL gradient buffer");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == PCX_F64) return backward_impl<double>(mlp, cx, grad_coords, gW, gb, st);
+    if (precision == PCX_F32) return backward_impl<float>(mlp, cx, grad_coords, gW, gb, st);
+    return fail(PCX_ERR_INVALID, "precision must be PCX_F64 or PCX_F32");
 }
 
 void pcx_cache_trim(void) { pool().trim(); }

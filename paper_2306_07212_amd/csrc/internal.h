@@ -69,6 +69,7 @@ struct Bufs {
     int *SELCNT;      // [kSelBlocks] per-chunk match counts of the compaction (also the pairing passes)
     int *CTR;         // [CTR_COUNT]
     const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
+    int2 *PQ;         // [Vcap] (V+, V-) parents of each new vertex, when the tape is recorded (else null)
 };
 
 // launchers (kernels.hip)
@@ -84,5 +85,15 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, h
 // `clear_n` entries of the table used by the previous step
 void launch_hash_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, HEntry *clear_t,
                       uint32_t clear_n, hipStream_t st);
+
+// backward (backward.hip)
+template <typename T>
+void bwd_init(const double *grad, T *gx, size_t n, T *gz, size_t nz, hipStream_t st);
+template <typename T>
+void bwd_step(const double *X, const double *Zs, const int2 *PQ, T *gx, T *gz, int D, int N, int ZS, int j, int V0,
+              int S, int *flag, hipStream_t st);
+template <typename T>
+void bwd_layer(const T *gz, int ZS, const double *hin, int hstride, int relu, int Vs, int N, int K, const double *W,
+               double *part, int chunks, double *gW, double *gb, T *gzp, int ZSp, hipStream_t st);
 
 }  // namespace pcx

@@ -511,6 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, 
             b.EDG[E0 + s] = make_int2((int)x0, ab.y);
             b.NXT[e] = da == kNoCol ? kNone : (uint16_t)da;
             b.NXT[E0 + s] = db == kNoCol ? kNone : (uint16_t)db;
+            if (b.PQ) b.PQ[x0] = apos ? ab : make_int2(ab.y, ab.x);
         }
         if (g.P > 0) {
             // exclusive prefix of key counts over the group's lanes

@@ -26,8 +26,9 @@ PAIRING = {"hash": 0, "sort": 1}
 SYMBOLS = [
     "pcx_last_error", "pcx_mlp_create", "pcx_mlp_free", "pcx_extract", "pcx_complex_info",
     "pcx_complex_steps", "pcx_complex_copy", "pcx_complex_device", "pcx_complex_kernel_time",
-    "pcx_complex_free", "pcx_cache_trim",
+    "pcx_complex_free", "pcx_cache_trim", "pcx_complex_copy_device", "pcx_backward",
 ]
+PCX_F64, PCX_F32 = 0, 1
 
 
 class PcxError(RuntimeError):
@@ -38,7 +39,7 @@ class PcxError(RuntimeError):
 
 class _Opts(C.Structure):
     _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("pairing", C.c_int32),
-                ("reserved1", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p)]
+                ("record_tape", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -66,6 +67,8 @@ def _load():
     lib.pcx_complex_kernel_time.argtypes = [vp, i32, PD, C.POINTER(i64)]
     lib.pcx_complex_free.argtypes = [vp]
     lib.pcx_complex_free.restype = None
+    lib.pcx_complex_copy_device.argtypes = [vp, vp, vp, vp, vp]
+    lib.pcx_backward.argtypes = [vp, vp, vp, C.POINTER(vp), C.POINTER(vp), i32, vp]
     lib.pcx_cache_trim.argtypes = []
     lib.pcx_cache_trim.restype = None
     for s in SYMBOLS:
@@ -198,6 +201,10 @@ class Complex:
         out[codes == 2] = -1
         return out
 
+    def copy_device(self, coords_ptr=None, signs_ptr=None, edges_ptr=None, stream=None):
+        """``pcx_complex_copy_device`` into caller-owned device buffers (raw pointers)."""
+        _check(_lib.pcx_complex_copy_device(self._h, coords_ptr, signs_ptr, edges_ptr, stream))
+
     def device_pointers(self):
         a, b, c = C.c_void_p(), C.c_void_p(), C.c_void_p()
         _check(_lib.pcx_complex_device(self._h, C.byref(a), C.byref(b), C.byref(c)))
@@ -226,15 +233,24 @@ def timing_mask(families) -> int:
     return sum(1 << KERNEL_FAMILIES.index(f) for f in families)
 
 
+def backward(mlp: MLP, cx: Complex, grad_coords_ptr: int, gW_ptrs, gb_ptrs, precision: int = PCX_F64,
+             stream=None) -> None:
+    """``pcx_backward``: dL/dW, dL/db (device buffers, overwritten) from dL/dx (device pointer)."""
+    L = len(mlp.widths) - 1
+    gw = (C.c_void_p * L)(*[int(p) for p in gW_ptrs])
+    gb = (C.c_void_p * L)(*[int(p) for p in gb_ptrs])
+    _check(_lib.pcx_backward(mlp._h, cx._h, grad_coords_ptr, gw, gb, int(precision), stream))
+
+
 def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=None,
-            max_bytes: int = 0, pairing: str = "hash") -> Complex:
+            max_bytes: int = 0, pairing: str = "hash", record_tape: bool = False) -> Complex:
     """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
     tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
-    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], 0, int(max_bytes), stream)
+    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream)
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))

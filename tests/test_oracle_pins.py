@@ -206,3 +206,22 @@ def test_planted_mistakes_are_caught(oracle_lib, mutation):
     cases = [(wl.he_mlp([2, 4, 4, 1], 24), wl.cube(2)), (wl.he_mlp([3, 4, 4, 1], 23), wl.cube(3))]
     assert all(_pins_pass(oracle_lib, n, b, 0) for n, b in cases)
     assert not all(_pins_pass(oracle_lib, n, b, mutation) for n, b in cases)
+
+
+# ------------------------------------------------- gradient closed form
+
+def test_implicit_gradient_matches_oracle_finite_differences(oracle_lib):
+    """The implicit-function gradient of the level-set edge loss (used to check
+    the GPU backward at full size) agrees with central differences of the
+    oracle's loss on a small net."""
+    from implicit import implicit_grad, level_set_loss, oracle_fd
+    net = wl.differentiable_small()
+    box = wl.cube(3)
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=True)
+    L, G, nedges = level_set_loss(r.X, r.S, r.edges, net.widths)
+    assert nedges > 10
+    gW, gb = implicit_grad(net, box.lo, box.hi, r.X, r.S, G)
+    fW, fb = oracle_fd(oracle_lib, net, box)
+    num = sum(np.sum((a - c) ** 2) for a, c in zip(gW + gb, fW + fb))
+    den = sum(np.sum(c ** 2) for c in fW + fb)
+    assert np.sqrt(num / den) < 1e-6, np.sqrt(num / den)
