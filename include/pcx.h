@@ -65,6 +65,8 @@ typedef struct {
                                pre-activations); costs V * N_l doubles per subdivided layer */
     uint64_t max_bytes;     /* cap on device bytes the extraction may hold; 0 = no cap */
     void *stream;           /* hipStream_t to run on; NULL = the default stream */
+    int32_t batch_wg_per_cu;/* pcx_extract_batch: workgroups per compute unit; 0 = tuned / default */
+    int32_t reserved;
 } pcx_opts;
 
 /* Summary of an extracted complex. */
@@ -130,6 +132,37 @@ int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void 
 int pcx_complex_kernel_time(const pcx_complex *cx, int32_t family, double *ms, int64_t *launches);
 
 void pcx_complex_free(pcx_complex *cx);
+
+/* ---- Batched extraction: many networks in one persistent launch ----------
+ * Each network is extracted exactly as pcx_extract would (same vertex and edge
+ * numbering, bit-identical values); a workgroup runs one network at a time
+ * from a largest-first queue. Networks that exceed the batched kernel's limits
+ * (D > 8, more than 8 layers, a layer wider than 256, or a predicted complex
+ * above 65536 vertices), or its per-workgroup arena, are extracted on the
+ * per-step path inside the same call. mlps[i] and the boxes lo/hi (the D_i
+ * coordinates of network i, concatenated over i; host memory) are read during
+ * the call. opts->include_output applies to every network. */
+typedef struct pcx_batch pcx_batch;
+typedef struct {
+    int64_t n, total_V, total_E, total_splits;
+    int32_t fallbacks;      /* networks extracted on the per-step path */
+    int32_t degenerate;     /* networks rejected as non-generic */
+    int32_t workgroups, wg_per_cu;
+    double kernel_ms;       /* device time of the persistent launch */
+    double time_ms;         /* host wall time of the whole call */
+} pcx_batch_stats;
+int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
+                      const pcx_opts *opts, pcx_batch **out);
+/* Per-network info / copy; PCX_ERR_DEGENERATE for a non-generic network. */
+int pcx_batch_info(const pcx_batch *bt, int32_t i, pcx_info *info);
+int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *signs, int32_t *edges);
+int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *stats);
+void pcx_batch_free(pcx_batch *bt);
+/* Autotuner: runs the batch once per candidate occupancy (1, 2, 4 workgroups
+ * per compute unit), keeps the fastest for batches with the same size
+ * signature (used by later pcx_extract_batch calls with batch_wg_per_cu = 0). */
+int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
+                   const pcx_opts *opts, int32_t *best_wg_per_cu);
 
 /* Gradient of a loss L(coordinates) with respect to every weight and bias,
  * through the vertex positions (Sec. 5.3: a loss on the extracted complex is

@@ -1,0 +1,57 @@
+// Descriptors of the persistent batched kernel (batch.hip) and its host side.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace pcx {
+
+constexpr int kBatchMaxLayers = 8;  // affine layers per network in a batch
+constexpr int kBatchMaxD = 8;       // input dimension in a batch
+constexpr int kBatchMaxWords = 64;  // sign-row words per vertex in a batch
+
+enum { BATCH_OK = 0, BATCH_OVERFLOW = 1, BATCH_POOL = 2, BATCH_DEGENERATE = 3, BATCH_INTERNAL = 4 };
+
+struct BatchNet {
+    const double *Wt[kBatchMaxLayers];  // transposed weights, [N_{l-1}][N_l]
+    const double *b[kBatchMaxLayers];
+    int widths[kBatchMaxLayers + 1];
+    int L, nsub, D;
+    double lo[kBatchMaxD], hi[kBatchMaxD];
+};
+
+struct BatchResult {
+    int status, V, E, Wd;
+    long long offV, offSG, offE;  // offsets into the output pool: doubles, sign words, edges
+    long long splits, pairs;
+};
+
+struct BatchArgs {
+    const BatchNet *nets;
+    int n;
+    const int *order;  // processing order (largest predicted network first)
+    int *ticket;
+    char *arena;       // one arena per workgroup
+    size_t arena_bytes, vbytes;  // per workgroup; vbytes = vertex region
+    int ecap, kcap;    // edges, 2-face key slots per workgroup
+    uint32_t tcap;     // hash-table entries per workgroup
+    double *oX;
+    uint64_t *oSG;
+    int2 *oE;
+    unsigned long long *pool;  // used: [0] coordinate doubles, [1] sign words, [2] edges
+    unsigned long long capV, capSG, capE;
+    BatchResult *res;
+};
+
+// bytes of one workgroup arena: vertex region + edges (14 B) + keys (12 B)
+// + table + valid words + counters
+inline size_t batch_arena_bytes(size_t vbytes, int ecap, int kcap, uint32_t tcap) {
+    size_t k = (size_t)kcap * 12;
+    k += 256 - k % 256;
+    return vbytes + (size_t)ecap * 16 + k + (size_t)tcap * sizeof(HEntry) + kBatchMaxWords * 8 + 256;
+}
+
+void launch_batch(const BatchArgs &A, int grid, hipStream_t st);
+
+}  // namespace pcx

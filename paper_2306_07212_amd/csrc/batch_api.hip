@@ -1,0 +1,366 @@
+// C ABI of the batched extraction (one persistent launch for many networks).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "batch.h"
+#include "host.h"
+
+using namespace pcx;
+
+struct pcx_batch {
+    int n = 0;
+    std::vector<int> D, Wd, M, nsteps;
+    std::vector<BatchResult> res;
+    std::vector<pcx_complex *> fallback;  // networks extracted on the per-step path
+    double *oX = nullptr;
+    uint64_t *oSG = nullptr;
+    int2 *oE = nullptr;
+    double time_ms = 0.0, kernel_ms = 0.0;
+    int workgroups = 0, wg_per_cu = 0, n_fallback = 0;
+};
+
+namespace {
+
+// Predicted vertex count of a random-init network: ~0.6 N^D / (D-1)! for N
+// subdivided neurons (fitted on the seeded workloads; only used to size
+// buffers and to order the queue, never for correctness).
+double predict_vertices(int D, int N) {
+    double f = 1.0;
+    for (int k = 2; k < D; ++k) f *= k;
+    return 0.6 * std::pow((double)N, D) / f + std::pow(2.0, D) + 4.0 * N;
+}
+
+std::mutex g_tune_mu;
+std::map<std::vector<int>, int> g_tuned;  // batch signature -> workgroups per CU
+
+}  // namespace
+
+extern "C" {
+
+int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
+                      const pcx_opts *opts, pcx_batch **out) {
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || (n > 0 && (!mlps || !lo || !hi))) return fail(PCX_ERR_INVALID, "NULL argument");
+    pcx_opts o{};
+    if (opts) o = *opts;
+    hipStream_t st = (hipStream_t)o.stream;
+    auto t_start = std::chrono::steady_clock::now();
+    auto *bt = new pcx_batch();
+    bt->n = n;
+    bt->res.assign(n, BatchResult{});
+    bt->fallback.assign(n, nullptr);
+    bt->D.resize(n);
+    bt->Wd.resize(n);
+    bt->M.resize(n);
+    bt->nsteps.resize(n);
+    std::vector<BatchNet> nets(n);
+    std::vector<double> pred(n);
+    std::vector<int> batched, direct;
+    size_t box_off = 0;
+    int maxD = 1, maxWd = 1, maxZS = 1;
+    double predV = 0;
+    for (int i = 0; i < n; ++i) {
+        const pcx_mlp *m = mlps[i];
+        if (!m) {
+            pcx_batch_free(bt);
+            return fail(PCX_ERR_INVALID, "NULL network");
+        }
+        const int D = m->D, L = m->L, nsub = o.include_output ? L : L - 1;
+        for (int j = 0; j < D; ++j)
+            if (!(lo[box_off + j] < hi[box_off + j])) {
+                pcx_batch_free(bt);
+                return fail(PCX_ERR_INVALID, "box must have lo < hi in every coordinate");
+            }
+        int Wd = 1, M = 2 * D, N = 0, ZS = 1;
+        bool fits = D <= kBatchMaxD && L <= kBatchMaxLayers;
+        for (int l = 1; l <= nsub; ++l) {
+            if (m->widths[l] > kMaxWidth) fits = false;
+            Wd += (m->widths[l] + 31) / 32;
+            M += m->widths[l];
+            N += m->widths[l];
+            ZS = std::max(ZS, m->widths[l]);
+        }
+        if (Wd > kBatchMaxWords) fits = false;
+        bt->D[i] = D;
+        bt->Wd[i] = Wd;
+        bt->M[i] = M;
+        bt->nsteps[i] = N;
+        pred[i] = predict_vertices(D, N);
+        if (pred[i] > 65536.0) fits = false;  // larger networks use the per-step path
+        if (fits) {
+            BatchNet &bn = nets[i];
+            std::memset(&bn, 0, sizeof bn);
+            for (int l = 0; l < L; ++l) {
+                bn.Wt[l] = m->Wt[l];
+                bn.b[l] = m->b[l];
+            }
+            for (int l = 0; l <= L; ++l) bn.widths[l] = m->widths[l];
+            bn.L = L;
+            bn.nsub = nsub;
+            bn.D = D;
+            for (int j = 0; j < D; ++j) {
+                bn.lo[j] = lo[box_off + j];
+                bn.hi[j] = hi[box_off + j];
+            }
+            batched.push_back(i);
+            maxD = std::max(maxD, D);
+            maxWd = std::max(maxWd, Wd);
+            maxZS = std::max(maxZS, ZS);
+            predV = std::max(predV, pred[i]);
+        } else {
+            direct.push_back(i);
+        }
+        box_off += D;
+    }
+    // largest predicted work first (the queue of the persistent kernel)
+    std::sort(batched.begin(), batched.end(), [&](int a, int b) {
+        return pred[a] * bt->nsteps[a] > pred[b] * bt->nsteps[b] || (pred[a] * bt->nsteps[a] == pred[b] * bt->nsteps[b] && a < b);
+    });
+    int rc = PCX_OK;
+    Arena ar;
+    ar.cap = o.max_bytes;
+    float kms = 0.f;
+    if (!batched.empty()) {
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // per-workgroup arena from the largest batched network
+        const int P = 2 * (maxD - 1) > 0 ? 2 * (maxD - 1) : 1;
+        size_t vcap = (size_t)(predV * 1.25) + 64;
+        size_t vbytes = vcap * 8 * (size_t)(maxD + maxWd + maxZS);
+        vbytes = (vbytes + 255) / 256 * 256;
+        int ecap = (int)(((size_t)vcap * (maxD + 1) + 15) / 16 * 16);
+        int kcap = (int)std::max<size_t>(1024, (size_t)P * std::max<size_t>(256, vcap / 12));
+        uint32_t tcap = 256;
+        while (tcap < 2u * (uint32_t)kcap) tcap <<= 1;
+        size_t abytes = batch_arena_bytes(vbytes, ecap, kcap, tcap);
+        abytes = (abytes + 255) / 256 * 256;
+        // workgroups per CU: from the autotuner's cache, else 2
+        std::vector<int> sig;
+        for (int i : batched) sig.push_back(bt->nsteps[i] * 16 + bt->D[i]);
+        std::sort(sig.begin(), sig.end());
+        int wpc = 2;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(sig);
+            if (it != g_tuned.end()) wpc = it->second;
+        }
+        if (o.batch_wg_per_cu > 0) wpc = o.batch_wg_per_cu;
+        int grid = std::min<int>((int)batched.size(), cus * wpc);
+        // output pool from the predictions (overflowing networks fall back)
+        double sv = 0, ssg = 0, se = 0;
+        for (int i : batched) {
+            const double v = std::min(pred[i], (double)vcap);
+            sv += v * bt->D[i];
+            ssg += v * bt->Wd[i];
+            se += v * (bt->D[i] + 1);
+        }
+        const unsigned long long capV = (unsigned long long)(sv * 1.1) + 1024, capSG = (unsigned long long)(ssg * 1.1) + 1024,
+                                 capE = (unsigned long long)(se * 1.1) + 1024;
+        void *p;
+        BatchArgs A{};
+        if ((rc = ar.alloc(&p, (size_t)grid * abytes))) goto fail_out;
+        A.arena = (char *)p;
+        if ((rc = ar.alloc(&p, capV * sizeof(double)))) goto fail_out;
+        bt->oX = (double *)p;
+        ar.forget(p);  // owned by the batch from here on
+        if ((rc = ar.alloc(&p, capSG * sizeof(uint64_t)))) goto fail_out;
+        bt->oSG = (uint64_t *)p;
+        ar.forget(p);  // owned by the batch from here on
+        if ((rc = ar.alloc(&p, capE * sizeof(int2)))) goto fail_out;
+        bt->oE = (int2 *)p;
+        ar.forget(p);  // owned by the batch from here on
+        if ((rc = ar.alloc(&p, (size_t)n * sizeof(BatchNet)))) goto fail_out;
+        A.nets = (const BatchNet *)p;
+        if ((rc = ar.alloc(&p, batched.size() * sizeof(int)))) goto fail_out;
+        A.order = (const int *)p;
+        if ((rc = ar.alloc(&p, 8 * sizeof(unsigned long long)))) goto fail_out;
+        A.pool = (unsigned long long *)p;
+        A.ticket = (int *)(A.pool + 4);
+        if ((rc = ar.alloc(&p, (size_t)n * sizeof(BatchResult)))) goto fail_out;
+        A.res = (BatchResult *)p;
+        A.n = (int)batched.size();
+        A.arena_bytes = abytes;
+        A.vbytes = vbytes;
+        A.ecap = ecap;
+        A.kcap = kcap;
+        A.tcap = tcap;
+        A.oX = bt->oX;
+        A.oSG = bt->oSG;
+        A.oE = bt->oE;
+        A.capV = capV;
+        A.capSG = capSG;
+        A.capE = capE;
+        {
+            HIPCHK(hipMemcpyAsync((void *)A.nets, nets.data(), (size_t)n * sizeof(BatchNet), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync((void *)A.order, batched.data(), batched.size() * sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemsetAsync(A.pool, 0, 8 * sizeof(unsigned long long), st));
+            hipEvent_t e0, e1;
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            HIPCHK(hipEventRecord(e0, st));
+            launch_batch(A, grid, st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipMemcpyAsync(bt->res.data(), A.res, (size_t)n * sizeof(BatchResult), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipEventElapsedTime(&kms, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+        bt->workgroups = grid;
+        bt->wg_per_cu = wpc;
+        for (int i : batched) {
+            const int s = bt->res[i].status;
+            if (s == BATCH_OVERFLOW || s == BATCH_POOL) direct.push_back(i);
+            else if (s == BATCH_INTERNAL) {
+                rc = fail(PCX_ERR_DEVICE, "internal error in the batched kernel");
+                goto fail_out;
+            }
+        }
+    }
+    bt->kernel_ms = kms;
+    // networks that do not fit the batched kernel: the per-step path
+    box_off = 0;
+    {
+        std::vector<size_t> offs(n);
+        for (int i = 0; i < n; ++i) {
+            offs[i] = box_off;
+            box_off += bt->D[i];
+        }
+        pcx_opts od = o;
+        for (int i : direct) {
+            pcx_complex *cx = nullptr;
+            int r = pcx_extract(mlps[i], lo + offs[i], hi + offs[i], &od, &cx);
+            BatchResult &br = bt->res[i];
+            std::memset(&br, 0, sizeof br);
+            if (r == PCX_ERR_DEGENERATE) {
+                br.status = BATCH_DEGENERATE;
+                continue;
+            }
+            if (r != PCX_OK) {
+                rc = r;
+                goto fail_out;
+            }
+            bt->fallback[i] = cx;
+            br.status = BATCH_OK;
+            br.V = (int)cx->V;
+            br.E = (int)cx->E;
+            br.Wd = cx->Wd;
+            br.splits = cx->total_splits;
+            br.pairs = cx->total_pairs;
+            bt->n_fallback++;
+        }
+    }
+    bt->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    *out = bt;
+    return PCX_OK;
+fail_out:
+    pcx_batch_free(bt);
+    return rc;
+}
+
+int pcx_batch_info(const pcx_batch *bt, int32_t i, pcx_info *info) {
+    if (!bt || !info || i < 0 || i >= bt->n) return fail(PCX_ERR_INVALID, "bad argument");
+    const BatchResult &r = bt->res[i];
+    if (r.status == BATCH_DEGENERATE) return fail(PCX_ERR_DEGENERATE, "network is not generic");
+    std::memset(info, 0, sizeof *info);
+    info->V = r.V;
+    info->E = r.E;
+    info->D = bt->D[i];
+    info->M = bt->M[i];
+    info->Wd = bt->Wd[i];
+    info->n_steps = bt->nsteps[i];
+    info->total_splits = r.splits;
+    info->total_pairs = r.pairs;
+    return PCX_OK;
+}
+
+int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *signs, int32_t *edges) {
+    if (!bt || i < 0 || i >= bt->n) return fail(PCX_ERR_INVALID, "bad argument");
+    const BatchResult &r = bt->res[i];
+    if (r.status == BATCH_DEGENERATE) return fail(PCX_ERR_DEGENERATE, "network is not generic");
+    if (bt->fallback[i]) return pcx_complex_copy(bt->fallback[i], coords, signs, edges);
+    const int D = bt->D[i];
+    if (coords)
+        HIPCHK(hipMemcpy(coords, bt->oX + (size_t)r.offV, (size_t)r.V * D * sizeof(double), hipMemcpyDeviceToHost));
+    if (signs)
+        HIPCHK(hipMemcpy(signs, bt->oSG + r.offSG, (size_t)r.V * r.Wd * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (edges) HIPCHK(hipMemcpy(edges, bt->oE + r.offE, (size_t)r.E * sizeof(int2), hipMemcpyDeviceToHost));
+    return PCX_OK;
+}
+
+int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *s) {
+    if (!bt || !s) return fail(PCX_ERR_INVALID, "NULL argument");
+    std::memset(s, 0, sizeof *s);
+    s->n = bt->n;
+    for (int i = 0; i < bt->n; ++i) {
+        const BatchResult &r = bt->res[i];
+        if (r.status == BATCH_DEGENERATE) {
+            s->degenerate++;
+            continue;
+        }
+        s->total_V += r.V;
+        s->total_E += r.E;
+        s->total_splits += r.splits;
+    }
+    s->fallbacks = bt->n_fallback;
+    s->workgroups = bt->workgroups;
+    s->wg_per_cu = bt->wg_per_cu;
+    s->kernel_ms = bt->kernel_ms;
+    s->time_ms = bt->time_ms;
+    return PCX_OK;
+}
+
+void pcx_batch_free(pcx_batch *bt) {
+    if (!bt) return;
+    pool().put(bt->oX);
+    pool().put(bt->oSG);
+    pool().put(bt->oE);
+    for (auto *c : bt->fallback) pcx_complex_free(c);
+    delete bt;
+}
+
+int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi, const pcx_opts *opts,
+                   int32_t *best_wg_per_cu) {
+    // try each occupancy, keep the fastest for this batch's size signature
+    static const int cand[] = {1, 2, 4};
+    double best = 1e300;
+    int bw = 2;
+    for (int w : cand) {
+        pcx_opts o{};
+        if (opts) o = *opts;
+        o.batch_wg_per_cu = w;
+        pcx_batch *bt = nullptr;
+        int rc = pcx_extract_batch(n, mlps, lo, hi, &o, &bt);
+        if (rc) return rc;
+        if (bt->kernel_ms < best) {
+            best = bt->kernel_ms;
+            bw = w;
+        }
+        pcx_batch_free(bt);
+    }
+    std::vector<int> sig;
+    const int incl = opts ? opts->include_output : 0;
+    for (int i = 0; i < n; ++i) {
+        int N = 0;
+        const int nsub = incl ? mlps[i]->L : mlps[i]->L - 1;
+        for (int l = 1; l <= nsub; ++l) N += mlps[i]->widths[l];
+        if (predict_vertices(mlps[i]->D, N) <= 65536.0 && mlps[i]->D <= kBatchMaxD && mlps[i]->L <= kBatchMaxLayers)
+            sig.push_back(N * 16 + mlps[i]->D);
+    }
+    std::sort(sig.begin(), sig.end());
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[sig] = bw;
+    }
+    if (best_wg_per_cu) *best_wg_per_cu = bw;
+    return PCX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Host-side helpers shared by the C ABI sources of libpcx.so (api.hip,
+// batch_api.hip): error reporting, the handle structs, the device block cache
+// and per-extraction arenas.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "pcx.h"
+
+namespace pcx {
+// Records msg as the calling thread's last error and returns code.
+int fail(int code, const std::string &msg);
+}  // namespace pcx
+
+#define HIPCHK(x)                                                                                      \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess) return pcx::fail(PCX_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct pcx_mlp {
+    int L = 0, D = 0;
+    std::vector<int> widths;
+    std::vector<double *> Wt;  // device, layer l: [N_{l-1}][N_l] (transposed for coalesced GEMM reads)
+    std::vector<double *> Wr;  // device, layer l: [N_l][N_{l-1}] as given (backward pass)
+    std::vector<double *> b;   // device, [N_l]
+    std::atomic<int64_t> hintV{0}, hintE{0};  // sizes seen by the last extraction (capacity hint)
+};
+
+struct pcx_complex {
+    int D = 0, M = 0, Wd = 0, n_steps = 0;
+    int64_t V = 0, E = 0;
+    double *X = nullptr;
+    uint64_t *SG = nullptr;
+    int2 *EDG = nullptr;
+    std::vector<int64_t> steps;
+    int64_t total_splits = 0, total_pairs = 0;
+    uint64_t peak = 0;
+    double time_ms = 0.0;
+    double ktime[PCX_K_COUNT] = {};
+    int64_t klaunch[PCX_K_COUNT] = {};
+    // tape (record_tape): parents of each new vertex, each subdivided layer's
+    // pre-activation rows at its end (stride ZS), and the first step of each layer
+    bool taped = false;
+    int ZS = 0, nsub = 0;
+    int2 *PQ = nullptr;
+    std::vector<double *> Zl;
+    std::vector<int> layer_step0;
+};
+
+
+namespace pcx {
+// Device blocks released by finished extractions are kept for reuse, per
+// device and size class, so that repeated extractions of large complexes do
+// not pay for hipMalloc / hipFree of tens of GB each time. pcx_cache_trim()
+// returns them to the runtime; a failed hipMalloc trims and retries once.
+struct Pool {
+    std::mutex m;
+    std::map<std::pair<int, size_t>, std::vector<void *>> cached;  // (device, bytes) -> blocks
+    std::unordered_map<void *, std::pair<int, size_t>> owned;       // every block handed out
+    uint64_t cached_bytes = 0;
+
+    static size_t size_class(size_t bytes) {
+        const size_t g = bytes >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
+        return (bytes + g - 1) / g * g;
+    }
+    // limit: largest block the caller may take (a cached block can be bigger than asked)
+    void *get(size_t bytes, size_t *got, size_t limit) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const size_t sz = size_class(bytes);
+        *got = sz;
+        {
+            // best fit among cached blocks of this device no larger than 1.6x the request
+            std::lock_guard<std::mutex> lk(m);
+            auto it = cached.lower_bound({dev, sz});
+            const size_t fit = std::min(limit, sz + sz / 2 + sz / 10);
+            for (; it != cached.end() && it->first.first == dev && it->first.second <= fit; ++it) {
+                if (it->second.empty()) continue;
+                void *p = it->second.back();
+                it->second.pop_back();
+                cached_bytes -= it->first.second;
+                *got = it->first.second;
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            if (hipMalloc(&p, sz) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        std::lock_guard<std::mutex> lk(m);
+        owned[p] = {dev, sz};
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(m);
+        auto it = owned.find(p);
+        if (it == owned.end()) return;
+        auto &v = cached[it->second];
+        if (std::find(v.begin(), v.end(), p) != v.end()) return;  // already returned
+        v.push_back(p);
+        cached_bytes += it->second.second;
+    }
+    void trim() {
+        std::lock_guard<std::mutex> lk(m);
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto &kv : cached) {
+            if (kv.first.first != cur) continue;
+            for (void *p : kv.second) {
+                (void)hipFree(p);
+                owned.erase(p);
+                cached_bytes -= kv.first.second;
+            }
+            kv.second.clear();
+        }
+    }
+};
+
+Pool &pool();
+
+// Device memory of one extraction, with a byte cap and peak accounting.
+struct Arena {
+    uint64_t cap = 0, cur = 0, peak = 0;
+    std::vector<std::pair<void *, size_t>> live;
+    int alloc(void **p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 256;
+        const size_t sz = Pool::size_class(bytes);
+        if (cap && cur + sz > cap)
+            return fail(PCX_ERR_CAPACITY, "extraction needs more device memory than max_bytes allows");
+        size_t got = 0;
+        *p = pool().get(bytes, &got, cap ? (size_t)(cap - cur) : ~(size_t)0);
+        if (!*p) return fail(PCX_ERR_OOM, "hipMalloc of " + std::to_string(sz) + " bytes failed");
+        live.push_back({*p, got});
+        cur += got;
+        peak = std::max(peak, cur);
+        return PCX_OK;
+    }
+    void release(void *p) {
+        if (!p) return;
+        for (size_t i = 0; i < live.size(); ++i)
+            if (live[i].first == p) {
+                cur -= live[i].second;
+                live.erase(live.begin() + i);
+                pool().put(p);
+                return;
+            }
+    }
+    void forget(void *p) {  // ownership moves out (to a pcx_complex)
+        for (size_t i = 0; i < live.size(); ++i)
+            if (live[i].first == p) {
+                live.erase(live.begin() + i);
+                return;
+            }
+    }
+    ~Arena() {
+        for (auto &a : live) pool().put(a.first);
+    }
+};
+
+}  // namespace pcx

@@ -7,85 +7,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device.h"
 #include "internal.h"
 
 namespace pcx {
-
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-    // 64-bit finaliser (splitmix64 constants, Steele et al. 2014)
-    x ^= x >> 30;
-    x *= 0xbf58476d1ce4e5b9ull;
-    x ^= x >> 27;
-    x *= 0x94d049bb133111ebull;
-    x ^= x >> 31;
-    return x;
-}
-
-// Hash of one sign-row word at position w; a row hashes to the sum over words,
-// so a single perturbed entry changes the hash in O(1).
-__device__ __forceinline__ uint64_t word_hash(int w, uint64_t v) {
-    return mix64(v + (uint64_t)(w + 1) * 0x9e3779b97f4a7c15ull);
-}
-
-// spread the 32 bits of x to the even bit positions of a 64-bit word
-__device__ __forceinline__ uint64_t part1by1(uint32_t x) {
-    uint64_t v = x;
-    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
-    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
-    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    v = (v | (v << 2)) & 0x3333333333333333ull;
-    v = (v | (v << 1)) & 0x5555555555555555ull;
-    return v;
-}
-
-// 2-bit codes of 32 entries from their positive / negative masks
-__device__ __forceinline__ uint64_t codes_of(uint32_t pos, uint32_t neg) {
-    return part1by1(pos) | (part1by1(neg) << 1);
-}
-
-// entries strictly before entry n = (wn, bn) inside word w
-__device__ __forceinline__ uint64_t lt_mask(int w, int wn, int bn) {
-    if (w < wn) return ~0ull;
-    if (w > wn) return 0ull;
-    return bn == 0 ? 0ull : ((1ull << bn) - 1ull);
-}
-
-// entries strictly after entry n inside this layer's words
-__device__ __forceinline__ uint64_t gt_mask(int w, int wn, int bn, int lw1) {
-    if (w < wn || w >= lw1) return 0ull;
-    if (w > wn) return ~0ull;
-    return bn + 2 >= 64 ? 0ull : ~((1ull << (bn + 2)) - 1ull);
-}
-
-constexpr int kNoCol = 0x7fffffff;
-
-__device__ __forceinline__ int first_col(uint64_t x, int w, int lw0) {
-    if (!x) return kNoCol;
-    return (w - lw0) * 32 + (__builtin_ctzll(x) >> 1);
-}
-
-__device__ __forceinline__ void raise_flag(int *ctr, int f) { atomicOr(&ctr[CTR_FLAGS], f); }
-
-template <int G, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    return v;
-}
-template <int G>
-__device__ __forceinline__ int group_min(int v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
-    return v;
-}
-template <int G>
-__device__ __forceinline__ int group_or(int v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, G);
-    return v;
-}
 
 // --------------------------------------------------------- step 0: the box
 
@@ -137,68 +62,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Bufs b, int ZS, const double 
                                                     const double *__restrict__ bias, int Wd, int lw0) {
     __shared__ double hs[kGemmRows][kGemmK + 1];
     __shared__ double ws[kGemmK][kMaxWidth];
-    const int t = threadIdx.x;
-    const int tc = t & 31, tv = t >> 5;
-    const int v0 = blockIdx.x * kGemmRows;
-    double acc[4][8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[i][c] = 0.0;
-
-    for (int k0 = 0; k0 < K; k0 += kGemmK) {
-        for (int idx = t; idx < kGemmRows * kGemmK; idx += kThreads) {
-            const int r = idx / kGemmK, k = idx % kGemmK;
-            const int v = v0 + r;
-            double h = 0.0;
-            if (v < V && k0 + k < K) {
-                h = in[(size_t)v * in_stride + k0 + k];
-                if (relu) h = h > 0.0 ? h : 0.0;
-            }
-            hs[r][k] = h;
-        }
-        for (int idx = t; idx < kGemmK * kMaxWidth; idx += kThreads) {
-            const int k = idx / kMaxWidth, c = idx % kMaxWidth;
-            ws[k][c] = (k0 + k < K && c < N) ? Wt[(size_t)(k0 + k) * N + c] : 0.0;
-        }
-        __syncthreads();
-        const int kc = min(kGemmK, K - k0);
-        for (int kk = 0; kk < kc; ++kk) {
-            double h[4], w[8];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = hs[tv * 4 + i][kk];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) w[c] = ws[kk][tc + 32 * c];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) acc[i][c] += h[i] * w[c];
-        }
-        __syncthreads();
-    }
-    const int half = (t >> 5) & 1;  // which 32-lane half of the wave holds this vertex group
-    const int nwords = (N + 31) >> 5;
-    int zero = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int v = v0 + tv * 4 + i;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int col = tc + 32 * c;
-            const bool ok = v < V && col < N;
-            double z = 0.0;
-            if (ok) {
-                z = acc[i][c] + bias[col];
-                b.Z[(size_t)v * ZS + col] = z;
-                zero |= (z == 0.0);
-            }
-            const uint64_t pb = __ballot(ok && z > 0.0);
-            const uint64_t nb = __ballot(ok && z < 0.0);
-            if (tc == 0 && v < V && c < nwords)
-                b.SG[(size_t)v * Wd + lw0 + c] = codes_of((uint32_t)(pb >> (32 * half)), (uint32_t)(nb >> (32 * half)));
-        }
-    }
-    if (zero) raise_flag(b.CTR, FLAG_ZERO_SIGN);
+    gemm_tile(b, ZS, in, in_stride, relu, V, K, N, Wt, bias, Wd, lw0, blockIdx.x * kGemmRows, hs, ws);
 }
 
 void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int relu, int V, int K, int N,
@@ -246,24 +110,6 @@ void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ehint, 
 // as the sum of the counts of the chunks before it, and writes the matching
 // ids in order (wave ballot / prefix sum inside each tile). No workgroup ever
 // waits on another, so the scan runs at streaming speed on all XCDs.
-__device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, int base, int E, uint16_t target) {
-    uint32_t hit = 0;
-    if (base + kSelItems <= E) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(nxt + base);
-        const uint4 a = p[0], c = p[1];
-        const uint32_t w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            if ((uint16_t)(w[i] & 0xFFFFu) == target) hit |= 1u << (2 * i);
-            if ((uint16_t)(w[i] >> 16) == target) hit |= 1u << (2 * i + 1);
-        }
-    } else {
-        for (int i = 0; i < kSelItems; ++i)
-            if (base + i < E && nxt[base + i] == target) hit |= 1u << i;
-    }
-    return hit;
-}
-
 __device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
     const int per = ((E + (int)gridDim.x - 1) / (int)gridDim.x + kSelItems - 1) / kSelItems * kSelItems;
     c0 = min(E, (int)blockIdx.x * per);
@@ -344,41 +190,6 @@ void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
     hipLaunchKernelGGL(k_sel_scatter, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
 }
 
-// ----------------------------------------------- 2-face hash table (f1)
-//
-// Open addressing with linear probing on the full 64-bit key. The first
-// splitting edge to reach a 2-face claims the slot with a 64-bit CAS and
-// records its key slot in `a`; the second finds the key and records itself in
-// `b`. A third arrival means the 2-face is not met by exactly two splitting
-// edges (Sec. 4.2.2) and raises FLAG_RUN.
-__device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H, uint32_t u, int *ctr) {
-    uint32_t h = (uint32_t)H & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const unsigned long long prev = atomicCAS(&T[h].key, 0ull, (unsigned long long)H);
-        if (prev == 0ull) {
-            T[h].a = u + 1;
-            return;
-        }
-        if (prev == (unsigned long long)H) {
-            if (atomicCAS(&T[h].b, 0u, u + 1) != 0u) raise_flag(ctr, FLAG_RUN);
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-    raise_flag(ctr, FLAG_BOUNDS);  // table full: cannot happen at load factor <= 1/2
-}
-
-__device__ __forceinline__ int hash_find(const HEntry *T, uint32_t mask, uint64_t H) {
-    uint32_t h = (uint32_t)H & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const unsigned long long k = T[h].key;
-        if (k == (unsigned long long)H) return (int)h;
-        if (k == 0ull) return -1;
-        h = (h + 1) & mask;
-    }
-    return -1;
-}
-
 // -------------------------------------------- steps 4-5a: split and keys
 //
 // One group of G lanes per splitting edge (p, q), p = V+ and q = V-:
@@ -401,161 +212,10 @@ __device__ __forceinline__ int hash_find(const HEntry *T, uint32_t mask, uint64_
 template <int G, int NC>
 __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, int E0, int S) {
     constexpr int groups = kThreads / G;
-    constexpr int wpc = G / 32;  // sign words per chunk
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
-    const int half = (threadIdx.x & 63) / G;  // G == 32: which half of the wave
-    const int D = g.D, Wd = g.Wd, ZS = g.ZS, j = g.j, N = g.Nl;
-    const int nw = g.lw1 - g.lw0;
-    for (int s = blockIdx.x * groups + grp; s < S; s += gridDim.x * groups) {
-        const int e = b.SPL[s];
-        if ((unsigned)e >= (unsigned)E0) {
-            if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
-            continue;
-        }
-        const int2 ab = b.EDG[e];
-        if ((unsigned)ab.x >= (unsigned)V0 || (unsigned)ab.y >= (unsigned)V0) {
-            if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
-            continue;
-        }
-        const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;
-        const uint64_t *Ra = b.SG + (size_t)ab.x * Wd, *Rb = b.SG + (size_t)ab.y * Wd;
-        // ---- loads
-        const double za = Za[j], zb = Zb[j];
-        double A[NC], B[NC];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int c = k * G + lane;
-            A[k] = c < N ? Za[c] : 0.0;
-            B[k] = c < N ? Zb[c] : 0.0;
-        }
-        const uint64_t wa0 = lane < Wd ? Ra[lane] : 0ull, wb0 = lane < Wd ? Rb[lane] : 0ull;
-        const double xa = lane < D ? b.X[(size_t)ab.x * D + lane] : 0.0;
-        const double xb = lane < D ? b.X[(size_t)ab.y * D + lane] : 0.0;
-        // ---- interpolation
-        const bool apos = za > 0.0;
-        const double zp = apos ? za : zb, zq = apos ? zb : za;
-        const double tt = zp / (zp - zq);
-        const size_t x0 = (size_t)V0 + s;
-        int bad = 0;
-        double Zx[NC];
-        uint64_t pb[NC], nb[NC];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int c = k * G + lane;
-            const bool in = c < N;
-            const double p = apos ? A[k] : B[k], q = apos ? B[k] : A[k];
-            const double z = (c == j) ? 0.0 : p + tt * (q - p);
-            if (in && c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
-            Zx[k] = z;
-            pb[k] = __ballot(in && z > 0.0);
-            nb[k] = __ballot(in && z < 0.0);
-        }
-        const double xp = apos ? xa : xb, xq = apos ? xb : xa;
-        const double x0c = xp + tt * (xq - xp);
-        // ---- sign row of x0, hash of the edge's sign-vector, zeros, next crossings
-        uint64_t hsum = 0, rx0 = 0, f0 = 0;
-        int nz = 0, nkeys = 0, da = kNoCol, db = kNoCol;
-        for (int w = lane, it = 0; w < Wd; w += G, ++it) {
-            const uint64_t wa = it == 0 ? wa0 : Ra[w], wb = it == 0 ? wb0 : Rb[w];
-            const uint64_t lt = lt_mask(w, g.wn, g.bn), gt = gt_mask(w, g.wn, g.bn, g.lw1);
-            const uint64_t f = (wa | wb) & lt;
-            if (f & (f >> 1) & 0x5555555555555555ull) bad |= FLAG_CONFLICT;
-            uint64_t cw = 0;
-            const int u = w - g.lw0;
-            if (u >= 0 && u < nw) {
-                const int ku = u / wpc, sh = 32 * (wpc == 2 ? (u & 1) : half);
-                uint64_t P = 0, Q = 0;
-#pragma unroll
-                for (int k = 0; k < NC; ++k)
-                    if (k == ku) {
-                        P = pb[k];
-                        Q = nb[k];
-                    }
-                cw = codes_of((uint32_t)(P >> sh), (uint32_t)(Q >> sh));
-            }
-            const uint64_t rx = f | (cw & gt);
-            if (it == 0) {
-                rx0 = rx;
-                f0 = f;
-            } else {
-                b.SG[x0 * Wd + w] = rx;
-            }
-            if (w <= g.wn) hsum += word_hash(w, f);
-            const uint64_t zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
-            const int zc = __popcll(zm);
-            nz += zc;
-            nkeys += (w == 0) ? zc : 2 * zc;  // box entries all live in word 0
-            da = min(da, first_col((wa ^ rx) & gt, w, g.lw0));
-            db = min(db, first_col((rx ^ wb) & gt, w, g.lw0));
-        }
-        hsum = group_sum<G>(hsum);
-        nz = group_sum<G>(nz);
-        const int ktot = group_sum<G>(nkeys);
-        da = group_min<G>(da);
-        db = group_min<G>(db);
-        bad = group_or<G>(bad);
-        // ---- stores
-        if (lane < D) b.X[x0 * D + lane] = x0c;
-        double *Zo = b.Z + x0 * ZS;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int c = k * G + lane;
-            if (c < N) Zo[c] = Zx[k];
-        }
-        if (lane < Wd) b.SG[x0 * Wd + lane] = rx0;
-        if (lane == 0) {
-            if (nz != D - 1 || ktot > g.P) bad |= FLAG_ZERO_COUNT;
-            if (bad) raise_flag(b.CTR, bad);
-            b.EDG[e] = make_int2(ab.x, (int)x0);
-            b.EDG[E0 + s] = make_int2((int)x0, ab.y);
-            b.NXT[e] = da == kNoCol ? kNone : (uint16_t)da;
-            b.NXT[E0 + s] = db == kNoCol ? kNone : (uint16_t)db;
-            if (b.PQ) b.PQ[x0] = apos ? ab : make_int2(ab.y, ab.x);
-        }
-        if (g.P > 0) {
-            // exclusive prefix of key counts over the group's lanes
-            int incl = nkeys;
-#pragma unroll
-            for (int o = 1; o < G; o <<= 1) {
-                const int y = __shfl_up(incl, o, G);
-                if (lane >= o) incl += y;
-            }
-            int r = incl - nkeys;
-            const size_t sbase = (size_t)s * g.P;
-            for (int w = lane, it = 0; w < Wd && nkeys; w += G, ++it) {
-                const uint64_t lt = lt_mask(w, g.wn, g.bn);
-                const uint64_t f = it == 0 ? f0 : ((Ra[w] | Rb[w]) & lt);
-                uint64_t zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
-                if (!zm) continue;
-                const uint64_t hw = word_hash(w, f);
-                while (zm) {
-                    const int bit = __builtin_ctzll(zm);
-                    zm &= zm - 1;
-                    for (int minus = 0; minus < (w == 0 ? 1 : 2); ++minus) {
-                        const uint64_t h = hsum - hw + word_hash(w, f | ((minus ? 2ull : 1ull) << bit));
-                        if (r < g.P) {
-                            const size_t slot = sbase + r;
-                            b.PINFO[slot] = ((uint32_t)w << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
-                            if (g.pair_mode == PAIR_SORT) {
-                                b.K32a[slot] = (uint32_t)(h >> 33);
-                                b.FULL[slot] = h;
-                            } else {
-                                const uint64_t hk = h | (1ull << 63);  // never 0 (= empty)
-                                b.FULL[slot] = hk;
-                                hash_insert(g.HT, g.hmask, hk, (uint32_t)slot, b.CTR);
-                            }
-                        }
-                        ++r;
-                    }
-                }
-            }
-            for (int rr = ktot + lane; rr < g.P; rr += G) {
-                if (g.pair_mode == PAIR_SORT) b.K32a[sbase + rr] = kSentinel;
-                else b.FULL[sbase + rr] = 0ull;
-            }
-        }
-    }
+    const int half = (threadIdx.x & 63) / G;
+    for (int s = blockIdx.x * groups + grp; s < S; s += gridDim.x * groups) split_one<G, NC>(b, g, V0, E0, s, lane, half);
 }
 
 void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st) {
@@ -703,32 +363,6 @@ void launch_sort(const Bufs &b, int n, hipStream_t st) {
 // is grouped by the full 64-bit hash. Every pair is verified by comparing the
 // two perturbed sign-vectors word by word. The new edge joins the two new
 // vertices; its sign is the face's with 0 at the current neuron (Sec. 4.2.2).
-__device__ void emit_pair(const Bufs &b, const StepGeom &g, int V0, int nslots, int sa, int sb, size_t out) {
-    if ((unsigned)sa >= (unsigned)nslots || (unsigned)sb >= (unsigned)nslots) {
-        raise_flag(b.CTR, FLAG_BOUNDS);
-        return;
-    }
-    const int xa = V0 + sa / g.P, xb = V0 + sb / g.P;
-    const uint32_t pa = b.PINFO[sa], pb = b.PINFO[sb];
-    const int wa = (int)(pa >> 8), wb = (int)(pb >> 8);
-    const uint64_t ca = ((pa & 1u) ? 2ull : 1ull) << ((pa >> 1) & 63u);
-    const uint64_t cb = ((pb & 1u) ? 2ull : 1ull) << ((pb >> 1) & 63u);
-    const uint64_t *Ra = b.SG + (size_t)xa * g.Wd, *Rb = b.SG + (size_t)xb * g.Wd;
-    bool same = b.FULL[sa] == b.FULL[sb];
-    for (int w = 0; w <= g.wn && same; ++w) {
-        const uint64_t lt = lt_mask(w, g.wn, g.bn);
-        const uint64_t fa = (Ra[w] & lt) | (w == wa ? ca : 0ull);
-        const uint64_t fb = (Rb[w] & lt) | (w == wb ? cb : 0ull);
-        same = fa == fb;
-    }
-    if (!same) raise_flag(b.CTR, FLAG_VERIFY);
-    int col = kNoCol;
-    for (int w = g.wn; w < g.lw1 && col == kNoCol; ++w)
-        col = first_col((Ra[w] ^ Rb[w]) & gt_mask(w, g.wn, g.bn, g.lw1), w, g.lw0);
-    b.EDG[out] = make_int2(xa, xb);
-    b.NXT[out] = col == kNoCol ? kNone : (uint16_t)col;
-}
-
 __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, int E1, int nslots) {
     const uint32_t *KS = b.K32a;
     const uint32_t *VS = b.VALa;
@@ -785,28 +419,6 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, h
 // Every valid key slot u finds its 2-face entry; the smaller of the two slots
 // owns the pair. Owners are emitted in slot order (chunk counts, then an
 // ordered scatter, as in the compaction), so the edge list is deterministic.
-__device__ __forceinline__ bool hash_owner(const Bufs &b, const StepGeom &g, int u, int nslots, int &partner) {
-    const uint64_t H = b.FULL[u];
-    if (H == 0ull) return false;
-    const int h = hash_find(g.HT, g.hmask, H);
-    if (h < 0) {
-        raise_flag(b.CTR, FLAG_BOUNDS);
-        return false;
-    }
-    const uint32_t a = g.HT[h].a, c = g.HT[h].b;
-    if (c == 0u || a == 0u) {
-        raise_flag(b.CTR, FLAG_RUN);
-        return false;
-    }
-    const uint32_t p = (a - 1 == (uint32_t)u) ? c - 1 : a - 1;
-    if (p >= (uint32_t)nslots) {
-        raise_flag(b.CTR, FLAG_BOUNDS);
-        return false;
-    }
-    partner = (int)p;
-    return (uint32_t)u < p;
-}
-
 __device__ __forceinline__ void pair_chunk(int n, int &c0, int &c1) {
     const int per = ((n + (int)gridDim.x - 1) / (int)gridDim.x + kPairItems - 1) / kPairItems * kPairItems;
     c0 = min(n, (int)blockIdx.x * per);

@@ -27,6 +27,8 @@ SYMBOLS = [
     "pcx_last_error", "pcx_mlp_create", "pcx_mlp_free", "pcx_extract", "pcx_complex_info",
     "pcx_complex_steps", "pcx_complex_copy", "pcx_complex_device", "pcx_complex_kernel_time",
     "pcx_complex_free", "pcx_cache_trim", "pcx_complex_copy_device", "pcx_backward",
+    "pcx_extract_batch", "pcx_batch_info", "pcx_batch_copy", "pcx_batch_summary", "pcx_batch_free",
+    "pcx_batch_tune",
 ]
 PCX_F64, PCX_F32 = 0, 1
 
@@ -39,7 +41,14 @@ class PcxError(RuntimeError):
 
 class _Opts(C.Structure):
     _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("pairing", C.c_int32),
-                ("record_tape", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p)]
+                ("record_tape", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p),
+                ("batch_wg_per_cu", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _BatchStats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("total_V", C.c_int64), ("total_E", C.c_int64), ("total_splits", C.c_int64),
+                ("fallbacks", C.c_int32), ("degenerate", C.c_int32), ("workgroups", C.c_int32),
+                ("wg_per_cu", C.c_int32), ("kernel_ms", C.c_double), ("time_ms", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -69,6 +78,13 @@ def _load():
     lib.pcx_complex_free.restype = None
     lib.pcx_complex_copy_device.argtypes = [vp, vp, vp, vp, vp]
     lib.pcx_backward.argtypes = [vp, vp, vp, C.POINTER(vp), C.POINTER(vp), i32, vp]
+    lib.pcx_extract_batch.argtypes = [i32, C.POINTER(vp), PD, PD, C.POINTER(_Opts), C.POINTER(vp)]
+    lib.pcx_batch_info.argtypes = [vp, i32, C.POINTER(_Info)]
+    lib.pcx_batch_copy.argtypes = [vp, i32, vp, vp, vp]
+    lib.pcx_batch_summary.argtypes = [vp, C.POINTER(_BatchStats)]
+    lib.pcx_batch_free.argtypes = [vp]
+    lib.pcx_batch_free.restype = None
+    lib.pcx_batch_tune.argtypes = [i32, C.POINTER(vp), PD, PD, C.POINTER(_Opts), C.POINTER(i32)]
     lib.pcx_cache_trim.argtypes = []
     lib.pcx_cache_trim.restype = None
     for s in SYMBOLS:
@@ -250,8 +266,86 @@ def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=Non
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
     tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
-    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream)
+    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream, 0, 0)
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))
     return Complex(h, mlp.widths, include_output)
+
+
+@dataclass
+class BatchStats:
+    n: int
+    total_V: int
+    total_E: int
+    total_splits: int
+    fallbacks: int
+    degenerate: int
+    workgroups: int
+    wg_per_cu: int
+    kernel_ms: float
+    time_ms: float
+
+
+def _batch_args(mlps, boxes):
+    arr = (C.c_void_p * len(mlps))(*[m._h.value for m in mlps])
+    lo = np.ascontiguousarray(np.concatenate([np.asarray(b[0], np.float64) for b in boxes]) if boxes else np.zeros(1))
+    hi = np.ascontiguousarray(np.concatenate([np.asarray(b[1], np.float64) for b in boxes]) if boxes else np.zeros(1))
+    return arr, lo, hi
+
+
+class Batch:
+    """``pcx_extract_batch``: many networks in one persistent launch."""
+
+    def __init__(self, mlps, boxes, include_output: bool = False, wg_per_cu: int = 0, stream=None,
+                 max_bytes: int = 0):
+        self.mlps = list(mlps)
+        self.include_output = include_output
+        arr, lo, hi = _batch_args(self.mlps, boxes)
+        PD = C.POINTER(C.c_double)
+        o = _Opts(int(bool(include_output)), 0, 0, 0, int(max_bytes), stream, int(wg_per_cu), 0)
+        h = C.c_void_p()
+        _check(_lib.pcx_extract_batch(len(self.mlps), arr, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD),
+                                      C.byref(o), C.byref(h)))
+        self._h = h
+
+    def __len__(self):
+        return len(self.mlps)
+
+    def info(self, i) -> Info:
+        x = _Info()
+        _check(_lib.pcx_batch_info(self._h, int(i), C.byref(x)))
+        return Info(x.V, x.E, x.D, x.M, x.Wd, x.n_steps, x.total_splits, x.total_pairs, x.peak_bytes, x.time_ms)
+
+    def copy(self, i):
+        inf = self.info(i)
+        X = np.empty((inf.V, inf.D), np.float64)
+        SG = np.empty((inf.V, inf.Wd), np.uint64)
+        Ed = np.empty((inf.E, 2), np.int32)
+        _check(_lib.pcx_batch_copy(self._h, int(i), X.ctypes.data, SG.ctypes.data, Ed.ctypes.data))
+        return X, SG, Ed
+
+    def stats(self) -> BatchStats:
+        x = _BatchStats()
+        _check(_lib.pcx_batch_summary(self._h, C.byref(x)))
+        return BatchStats(x.n, x.total_V, x.total_E, x.total_splits, x.fallbacks, x.degenerate, x.workgroups,
+                          x.wg_per_cu, x.kernel_ms, x.time_ms)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pcx_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def batch_tune(mlps, boxes, include_output: bool = False) -> int:
+    """``pcx_batch_tune``: best workgroups per compute unit for this batch's sizes."""
+    arr, lo, hi = _batch_args(list(mlps), boxes)
+    PD = C.POINTER(C.c_double)
+    o = _Opts(int(bool(include_output)), 0, 0, 0, 0, None, 0, 0)
+    best = C.c_int32()
+    _check(_lib.pcx_batch_tune(len(mlps), arr, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o),
+                               C.byref(best)))
+    return best.value
