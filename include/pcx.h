@@ -164,6 +164,52 @@ void pcx_batch_free(pcx_batch *bt);
 int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
                    const pcx_opts *opts, int32_t *best_wg_per_cu);
 
+/* ---- Extraction server: continuous batching of requests -------------------
+ * Requests are queued in arrival order and admitted in that order while the
+ * predicted device memory of admitted, unfinished jobs fits mem_budget (a job
+ * is always admitted onto an idle GPU). Small networks (predicted complex of
+ * at most small_vertices vertices) are gathered into back-to-back ticks of the
+ * batched kernel; whatever arrives during a tick joins the next one. Larger
+ * networks run on the per-step path in large_workers threads, each on its own
+ * stream, overlapping with the ticks. A result is exactly the complex
+ * pcx_extract returns for the same request. The server keeps the pcx_mlp
+ * handle of a request until that request is released: the caller must not
+ * free it before. Latency = completion - submission (host steady clock). */
+typedef struct pcx_server pcx_server;
+typedef struct {
+    uint64_t mem_budget;    /* bytes of predicted device memory in flight; 0 = 64 GiB */
+    int32_t max_batch;      /* jobs per tick; 0 = 4096 */
+    int32_t large_workers;  /* concurrent per-step extractions; 0 = 3 */
+    int32_t include_output; /* as pcx_opts.include_output, for every request */
+    int32_t small_vertices; /* batched-kernel threshold on the predicted vertex count; 0 = 65536 */
+} pcx_server_opts;
+typedef struct {
+    int32_t status;         /* PCX_PENDING, PCX_OK or the error of the request */
+    int32_t batched;        /* 1: ran in a batched tick, 0: on the per-step path */
+    int64_t V, E, total_splits;
+    double latency_ms, queue_ms;  /* submission to completion / to admission */
+} pcx_server_result;
+typedef struct {
+    int64_t completed;
+    double p50_ms, p99_ms, mean_ms, p50_queue_ms, p99_queue_ms;
+    double span_s;          /* first submission to last completion */
+    double jobs_per_s, splits_per_s, vertices_per_s;
+    int64_t ticks;
+    double mean_tick_jobs;
+} pcx_server_summary;
+int pcx_server_create(const pcx_server_opts *opts, pcx_server **out);
+int pcx_server_submit(pcx_server *s, const pcx_mlp *mlp, const double *lo, const double *hi, uint64_t *ticket);
+/* PCX_PENDING while the request runs; PCX_OK once *r holds its outcome. */
+int pcx_server_poll(pcx_server *s, uint64_t ticket, pcx_server_result *r);
+int pcx_server_wait(pcx_server *s, uint64_t ticket, pcx_server_result *r);
+/* Copy a finished request's complex to host buffers (as pcx_complex_copy). */
+int pcx_server_copy(pcx_server *s, uint64_t ticket, double *coords, uint64_t *signs, int32_t *edges);
+/* Free a finished request's result (and drop the server's use of its mlp). */
+int pcx_server_release(pcx_server *s, uint64_t ticket);
+int pcx_server_stats(pcx_server *s, pcx_server_summary *stats);
+/* Waits for every submitted request, then stops the server's threads. */
+void pcx_server_destroy(pcx_server *s);
+
 /* Gradient of a loss L(coordinates) with respect to every weight and bias,
  * through the vertex positions (Sec. 5.3: a loss on the extracted complex is
  * optimised through its vertices). cx must come from pcx_extract of the same

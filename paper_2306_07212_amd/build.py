@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcx.so")
-SOURCES = ["kernels.hip", "backward.hip", "batch.hip", "api.hip", "batch_api.hip"]
+SOURCES = ["kernels.hip", "backward.hip", "batch.hip", "api.hip", "batch_api.hip", "server.hip"]
 
 
 def hipcc() -> str:
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

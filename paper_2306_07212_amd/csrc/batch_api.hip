@@ -25,15 +25,6 @@ struct pcx_batch {
 
 namespace {
 
-// Predicted vertex count of a random-init network: ~0.6 N^D / (D-1)! for N
-// subdivided neurons (fitted on the seeded workloads; only used to size
-// buffers and to order the queue, never for correctness).
-double predict_vertices(int D, int N) {
-    double f = 1.0;
-    for (int k = 2; k < D; ++k) f *= k;
-    return 0.6 * std::pow((double)N, D) / f + std::pow(2.0, D) + 4.0 * N;
-}
-
 std::mutex g_tune_mu;
 std::map<std::vector<int>, int> g_tuned;  // batch signature -> workgroups per CU
 

@@ -28,7 +28,8 @@ SYMBOLS = [
     "pcx_complex_steps", "pcx_complex_copy", "pcx_complex_device", "pcx_complex_kernel_time",
     "pcx_complex_free", "pcx_cache_trim", "pcx_complex_copy_device", "pcx_backward",
     "pcx_extract_batch", "pcx_batch_info", "pcx_batch_copy", "pcx_batch_summary", "pcx_batch_free",
-    "pcx_batch_tune",
+    "pcx_batch_tune", "pcx_server_create", "pcx_server_submit", "pcx_server_poll", "pcx_server_wait",
+    "pcx_server_copy", "pcx_server_release", "pcx_server_stats", "pcx_server_destroy",
 ]
 PCX_F64, PCX_F32 = 0, 1
 
@@ -55,6 +56,23 @@ class _Info(C.Structure):
     _fields_ = [("V", C.c_int64), ("E", C.c_int64), ("D", C.c_int32), ("M", C.c_int32), ("Wd", C.c_int32),
                 ("n_steps", C.c_int32), ("total_splits", C.c_int64), ("total_pairs", C.c_int64),
                 ("peak_bytes", C.c_uint64), ("time_ms", C.c_double)]
+
+
+class _ServerOpts(C.Structure):
+    _fields_ = [("mem_budget", C.c_uint64), ("max_batch", C.c_int32), ("large_workers", C.c_int32),
+                ("include_output", C.c_int32), ("small_vertices", C.c_int32)]
+
+
+class _ServerResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batched", C.c_int32), ("V", C.c_int64), ("E", C.c_int64),
+                ("total_splits", C.c_int64), ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
+
+
+class _ServerSummary(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("p50_queue_ms", C.c_double), ("p99_queue_ms", C.c_double), ("span_s", C.c_double),
+                ("jobs_per_s", C.c_double), ("splits_per_s", C.c_double), ("vertices_per_s", C.c_double),
+                ("ticks", C.c_int64), ("mean_tick_jobs", C.c_double)]
 
 
 def _load():
@@ -85,6 +103,16 @@ def _load():
     lib.pcx_batch_free.argtypes = [vp]
     lib.pcx_batch_free.restype = None
     lib.pcx_batch_tune.argtypes = [i32, C.POINTER(vp), PD, PD, C.POINTER(_Opts), C.POINTER(i32)]
+    u64p = C.POINTER(C.c_uint64)
+    lib.pcx_server_create.argtypes = [C.POINTER(_ServerOpts), C.POINTER(vp)]
+    lib.pcx_server_submit.argtypes = [vp, vp, PD, PD, u64p]
+    lib.pcx_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(_ServerResult)]
+    lib.pcx_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(_ServerResult)]
+    lib.pcx_server_copy.argtypes = [vp, C.c_uint64, vp, vp, vp]
+    lib.pcx_server_release.argtypes = [vp, C.c_uint64]
+    lib.pcx_server_stats.argtypes = [vp, C.POINTER(_ServerSummary)]
+    lib.pcx_server_destroy.argtypes = [vp]
+    lib.pcx_server_destroy.restype = None
     lib.pcx_cache_trim.argtypes = []
     lib.pcx_cache_trim.restype = None
     for s in SYMBOLS:
@@ -349,3 +377,75 @@ def batch_tune(mlps, boxes, include_output: bool = False) -> int:
     _check(_lib.pcx_batch_tune(len(mlps), arr, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o),
                                C.byref(best)))
     return best.value
+
+
+def _as_dict(st):
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+class Server:
+    """``pcx_server_*``: continuous batching of extraction requests."""
+
+    def __init__(self, mem_budget: int = 0, max_batch: int = 0, large_workers: int = 0,
+                 include_output: bool = False, small_vertices: int = 0):
+        o = _ServerOpts(int(mem_budget), int(max_batch), int(large_workers), int(bool(include_output)),
+                        int(small_vertices))
+        h = C.c_void_p()
+        _check(_lib.pcx_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}  # ticket -> (mlp, lo, hi): handles stay alive until release
+
+    def submit(self, mlp: MLP, lo, hi) -> int:
+        lo = np.ascontiguousarray(lo, np.float64)
+        hi = np.ascontiguousarray(hi, np.float64)
+        PD = C.POINTER(C.c_double)
+        t = C.c_uint64()
+        _check(_lib.pcx_server_submit(self._h, mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(t)))
+        self._keep[t.value] = (mlp, lo, hi)
+        return t.value
+
+    def poll(self, ticket: int):
+        r = _ServerResult()
+        rc = _lib.pcx_server_poll(self._h, C.c_uint64(ticket), C.byref(r))
+        if rc == PCX_PENDING:
+            return None
+        _check(rc)
+        return _as_dict(r)
+
+    def wait(self, ticket: int):
+        r = _ServerResult()
+        _check(_lib.pcx_server_wait(self._h, C.c_uint64(ticket), C.byref(r)))
+        return _as_dict(r)
+
+    def copy(self, ticket: int):
+        r = self.wait(ticket)
+        if r["status"] != PCX_OK:
+            raise PcxError(r["status"], "request failed")
+        mlp = self._keep[ticket][0]
+        D = mlp.D
+        Wd = 1
+        for n in mlp.widths[1:-1]:
+            Wd += (n + 31) // 32
+        X = np.empty((r["V"], D), np.float64)
+        SG = np.empty((r["V"], Wd), np.uint64)
+        Ed = np.empty((r["E"], 2), np.int32)
+        _check(_lib.pcx_server_copy(self._h, C.c_uint64(ticket), X.ctypes.data, SG.ctypes.data, Ed.ctypes.data))
+        return X, SG, Ed
+
+    def release(self, ticket: int):
+        _check(_lib.pcx_server_release(self._h, C.c_uint64(ticket)))
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        st = _ServerSummary()
+        _check(_lib.pcx_server_stats(self._h, C.byref(st)))
+        return _as_dict(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pcx_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()
