@@ -105,6 +105,149 @@ def cpu_baseline(net, half=0.06):
                       f"(all 768 neurons): {r.V} vertices, {r.E} edges, {splits} splits in {dt:.1f} s"}
 
 
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, np.float64), q)) if len(v) else 0.0
+
+
+def form_batched(args, pcx, wl, torch):
+    """4096 networks 2-[w]xd-1 in one persistent launch vs the per-step path."""
+    nets = wl.batch_nets()
+    box = wl.cube(2)
+    mlps = [pcx.MLP.from_net(n) for n in nets]
+    boxes = [(box.lo, box.hi)] * len(nets)
+    wpc = pcx.batch_tune(mlps, boxes)
+    for _ in range(max(1, args.warmup)):
+        pcx.Batch(mlps, boxes).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt = pcx.Batch(mlps, boxes)
+        st = bt.stats()
+        bt.close()
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    # per-step path on a stratified sample (every 16th network), scaled by splits
+    sample = list(range(0, len(nets), 16))
+    t1 = time.perf_counter()
+    s_splits = 0
+    for i in sample:
+        cx = pcx.extract(mlps[i], box.lo, box.hi)
+        s_splits += cx.info().total_splits
+        cx.close()
+    t_sample = time.perf_counter() - t1
+    plain_rate = s_splits / t_sample
+    return {"metric": METRIC, "value": st.total_splits / T, "unit": "edges subdivided/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": T * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "batched: 4096 MLPs 2-[w]xd-1, w in {8,16,32,64}, d in {2,3,4}, seeds (3, i), "
+                                   "box [-1,1]^2, one persistent launch", "parallelism": "single GPU"},
+            "vertices_per_s": st.total_V / T, "edges_per_s": st.total_E / T, "V": st.total_V, "E": st.total_E,
+            "splits": st.total_splits, "kernel_ms": st.kernel_ms, "workgroups": st.workgroups,
+            "wg_per_cu_tuned": wpc, "fallbacks": st.fallbacks,
+            "plain_path": {"edges_subdivided_per_s": plain_rate, "sample": f"{len(sample)} of 4096 networks "
+                           f"extracted one by one with pcx_extract in {t_sample:.2f} s"},
+            "speedup_vs_plain": (st.total_splits / T) / plain_rate}
+
+
+def form_served(args, pcx, wl, torch):
+    """Poisson stream of 2000 requests (D in {2,3}, widths 16-128, depths 2-4):
+    continuous batching vs the per-step path as a FIFO single server."""
+    reqs = wl.serve_requests(2000, rate_per_s=1.0)
+    unit = np.array([r.arrival_s for r in reqs])          # unit-rate arrival times
+    mlps = [pcx.MLP.from_net(r.net) for r in reqs]
+    # per-step path: service time of every request alone
+    svc = np.empty(len(reqs))
+    for i, (r, m) in enumerate(zip(reqs, mlps)):
+        t = time.perf_counter()
+        cx = pcx.extract(m, r.box.lo, r.box.hi)
+        cx.close()
+        svc[i] = time.perf_counter() - t
+        if i % 250 == 0:
+            print(f"[bench] served: plain service times {i}/{len(reqs)}", file=sys.stderr, flush=True)
+    mu = len(reqs) / svc.sum()  # saturation throughput of the per-step path (requests/s)
+    out_rates = []
+    for f in (0.25, 0.5, 1.0, 1.5, 2.0):
+        lam = f * mu
+        arr = unit / lam
+        # FIFO single server with the measured service times (the per-step path, one request at a time)
+        fin = np.empty(len(reqs))
+        tcur = 0.0
+        for i in range(len(reqs)):
+            tcur = max(tcur, arr[i]) + svc[i]
+            fin[i] = tcur
+        lat_plain = (fin - arr) * 1e3
+        srv = pcx.Server()
+        t0 = time.perf_counter()
+        tickets = []
+        for a, r, m in zip(arr, reqs, mlps):
+            dt = a - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(m, r.box.lo, r.box.hi))
+        res = [srv.wait(tk) for tk in tickets]
+        st = srv.stats()
+        for tk in tickets:
+            srv.release(tk)
+        srv.close()
+        assert all(x["status"] == 0 for x in res)
+        out_rates.append({"rate_x_plain_saturation": f, "rate_per_s": lam,
+                          "served": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "jobs_per_s": st["jobs_per_s"],
+                                     "splits_per_s": st["splits_per_s"], "ticks": st["ticks"],
+                                     "mean_tick_jobs": st["mean_tick_jobs"],
+                                     "batched_fraction": float(np.mean([x["batched"] for x in res]))},
+                          "plain_fifo": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
+                                         "jobs_per_s": len(reqs) / fin[-1]}})
+        print(f"[bench] served rate {f}x: {json.dumps(out_rates[-1])}", file=sys.stderr, flush=True)
+    mid = out_rates[2]
+    return {"metric": METRIC, "value": mid["served"]["p99_ms"], "unit": "ms (p99 latency at the plain path's "
+            "saturation rate)", "n_gpus": 1, "steps": len(reqs), "warmup": 0, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "served: Poisson stream of 2000 requests, D in {2,3}, constant width U[16,128], "
+                                   "depth U{2,3,4}, box [-1,1]^D, seeds (4, i)", "parallelism": "single GPU"},
+            "plain_saturation_req_per_s": mu, "plain_mean_service_ms": float(svc.mean() * 1e3), "rates": out_rates}
+
+
+def form_backward(args, pcx, wl, torch):
+    """3-64-64-64-1 level set: extraction with tape + loss + hand-written backward."""
+    from paper_2306_07212_amd import torch_ops as T
+    net = wl.differentiable()
+    box = wl.cube(3)
+    dev = torch.device("cuda:0")
+    res = {}
+    grads = {}
+    for prec in ("f64", "f32"):
+        Ws = [torch.tensor(w, dtype=torch.float64, device=dev, requires_grad=True) for w in net.W]
+        bs = [torch.tensor(x, dtype=torch.float64, device=dev, requires_grad=True) for x in net.b]
+        for it in range(args.warmup + args.steps):
+            if it == args.warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tb = 0.0
+            for p in Ws + bs:
+                p.grad = None
+            X, SG, Ed = T.extract_coords(Ws, bs, box.lo, box.hi, include_output=True, precision=prec)
+            loss = T.level_set_edge_loss(X, SG, Ed, net.widths)
+            torch.cuda.synchronize()
+            tb0 = time.perf_counter()
+            loss.backward()
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                tb += time.perf_counter() - tb0
+        T_all = (time.perf_counter() - t0) / args.steps
+        grads[prec] = [p.grad.detach().cpu().numpy() for p in Ws + bs]
+        res[prec] = {"ms_per_step": T_all * 1e3, "backward_ms": tb / args.steps * 1e3, "V": int(X.shape[0])}
+    num = sum(float(np.sum((a - b) ** 2)) for a, b in zip(grads["f32"], grads["f64"]))
+    den = sum(float(np.sum(b ** 2)) for b in grads["f64"])
+    V = res["f64"]["V"]
+    return {"metric": METRIC, "value": V / (res["f32"]["ms_per_step"] / 1e3), "unit": "vertices/s (extract + loss "
+            "+ FP32 backward)", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": res["f32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64 forward, f32 backward", "data": "synthetic",
+            "config": {"workload": "differentiable: MLP 3-64-64-64-1 with the output's level set, loss = sum of "
+                                   "squared lengths of level-set edges, box [-1,1]^3", "parallelism": "single GPU"},
+            "fp64": res["f64"], "fp32": res["f32"], "fp32_rel_error_vs_fp64": (num / den) ** 0.5}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +256,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain_large", help="workloads function name (default: the 768-neuron net)")
     ap.add_argument("--pairing", default="hash", choices=["hash", "sort"], help="step-5 grouping of 2-face keys")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "backward"],
+                    help="plain (default): one large network; the others measure the systems forms")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one 1 GiB device copy (reads 1 GiB, writes 1 GiB): the reference for "
+                         "scaling hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -122,6 +270,17 @@ def main():
     import torch
     from paper_2306_07212_amd import pcx
     from paper_2306_07212_amd import workloads as wl
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.form != "plain":
+        fn = {"batched": form_batched, "served": form_served, "backward": form_backward}[args.form]
+        print(json.dumps(fn(args, pcx, wl, torch)), flush=True)
+        return
 
     net = getattr(wl, args.workload)()
     D = net.D

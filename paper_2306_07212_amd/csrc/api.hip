@@ -438,6 +438,8 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
             g.wn = lw[l] + (j >> 5);
             g.bn = 2 * (j & 31);
             g.P = x.P;
+            // in the last subdivided layer nothing reads the processed columns again
+            g.zlo = (l == nsub - 1 && !x.tape) ? j + 1 : 0;
             g.pair_mode = x.pair_mode;
             g.HT = nullptr;
             g.hmask = 0;

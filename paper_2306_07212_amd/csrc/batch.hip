@@ -97,8 +97,8 @@ __device__ __forceinline__ void block_split(const Bufs &b, const StepGeom &g, in
     for (int s = grp; s < S; s += groups) split_one<G, NC>(b, g, V0, E0, s, lane, half);
 }
 
-__device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b, double (*hs)[kGemmK + 1],
-                        double (*ws)[kMaxWidth], int *s_w, int *s_misc) {
+__device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b, GemmLds *gl, int *s_w,
+                        int *s_misc) {
     const int t = threadIdx.x;
     const int D = net.D, nsub = net.nsub;
     int lw[kBatchMaxLayers + 1];
@@ -176,7 +176,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
         // step 1 for the layer, in place, one 32-row tile at a time
         for (int v0 = 0; v0 < V; v0 += kGemmRows)
             gemm_tile(b, ZS, l == 0 ? b.X : b.Z, l == 0 ? D : ZS, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l], v0,
-                      hs, ws);
+                      gl->hs, gl->ws);
         __syncthreads();
         for (int e = t; e < E; e += kThreads) {
             const int2 ab = b.EDG[e];
@@ -215,6 +215,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             g.pair_mode = PAIR_HASH;
             g.HT = table;
             g.hmask = tsz - 1;
+            g.zlo = 0;
             if (P > 0) {
                 for (uint32_t i = t; i < tsz; i += kThreads) {
                     HEntry z;
@@ -285,8 +286,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
 }
 
 __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
-    __shared__ double hs[kGemmRows][kGemmK + 1];
-    __shared__ double ws[kGemmK][kMaxWidth];
+    __shared__ GemmLds gl;
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_misc[8];
     __shared__ int s_net;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
         __syncthreads();
         if (k >= A.n) break;
         const int ni = A.order[k];
-        run_net(A, A.nets[ni], ni, b, hs, ws, s_w, s_misc);
+        run_net(A, A.nets[ni], ni, b, &gl, s_w, s_misc);
     }
 }
 

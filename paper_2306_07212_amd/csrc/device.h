@@ -128,14 +128,15 @@ __device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H
     raise_flag(ctr, FLAG_BOUNDS);  // table full: cannot happen at load factor <= 1/2
 }
 
-// Table words are read with device-scope atomic loads: within one persistent
-// launch the entries were last written by atomics of other waves, and such
-// loads never return a stale L1 line.
+// Table words are read with workgroup-scope atomic loads, which skip the L1:
+// inside the persistent batched kernel the entries were last written by
+// atomics of other waves of the same workgroup (one CU, one L2); across the
+// per-step kernels a launch boundary already orders them.
 __device__ __forceinline__ unsigned long long load_key(const HEntry *T, uint32_t h) {
-    return __hip_atomic_load(&T[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(&T[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ uint32_t load_u32(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ int hash_find(const HEntry *T, uint32_t mask, uint64_t H) {
@@ -267,6 +268,12 @@ __device__ __forceinline__ void gemm_tile(const Bufs &b, int ZS, const double *i
     if (zero) raise_flag(b.CTR, FLAG_ZERO_SIGN);
 }
 
+// LDS staging of one evaluation tile (gemm_tile)
+struct GemmLds {
+    double hs[kGemmRows][kGemmK + 1];
+    double ws[kGemmK][kMaxWidth];
+};
+
 // -------------------------------------------- steps 4-5a: split and keys
 // The work of one splitting edge s for a group of G lanes (lane = 0..G-1;
 // half = which 32-lane half of the wave the group is, for G = 32).
@@ -294,8 +301,9 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
-        A[k] = c < N ? Za[c] : 0.0;
-        B[k] = c < N ? Zb[c] : 0.0;
+        const bool live = c < N && c >= g.zlo;
+        A[k] = live ? Za[c] : 0.0;
+        B[k] = live ? Zb[c] : 0.0;
     }
     const uint64_t wa0 = lane < Wd ? Ra[lane] : 0ull, wb0 = lane < Wd ? Rb[lane] : 0ull;
     const double xa = lane < D ? b.X[(size_t)ab.x * D + lane] : 0.0;
@@ -369,7 +377,7 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
-        if (c < N) Zo[c] = Zx[k];
+        if (c < N && c >= g.zlo) Zo[c] = Zx[k];
     }
     if (lane < Wd) b.SG[x0 * Wd + lane] = rx0;
     if (lane == 0) {
@@ -382,40 +390,54 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
         if (b.PQ) b.PQ[x0] = apos ? ab : make_int2(ab.y, ab.x);
     }
     if (g.P > 0) {
-        // exclusive prefix of key counts over the group's lanes
-        int incl = nkeys;
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            const int y = __shfl_up(incl, o, G);
-            if (lane >= o) incl += y;
-        }
-        int r = incl - nkeys;
-        const size_t sbase = (size_t)s * g.P;
-        for (int w = lane, it = 0; w < Wd && nkeys; w += G, ++it) {
-            const uint64_t lt = lt_mask(w, g.wn, g.bn);
-            const uint64_t f = it == 0 ? f0 : ((Ra[w] | Rb[w]) & lt);
-            uint64_t zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
-            if (!zm) continue;
-            const uint64_t hw = word_hash(w, f);
-            while (zm) {
-                const int bit = __builtin_ctzll(zm);
-                zm &= zm - 1;
-                for (int minus = 0; minus < (w == 0 ? 1 : 2); ++minus) {
-                    const uint64_t h = hsum - hw + word_hash(w, f | ((minus ? 2ull : 1ull) << bit));
-                    if (r < g.P) {
-                        const size_t slot = sbase + r;
-                        b.PINFO[slot] = ((uint32_t)w << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
-                        if (g.pair_mode == PAIR_SORT) {
-                            b.K32a[slot] = (uint32_t)(h >> 33);
-                            b.FULL[slot] = h;
-                        } else {
-                            const uint64_t hk = h | (1ull << 63);  // never 0 (= empty)
-                            b.FULL[slot] = hk;
-                            hash_insert(g.HT, g.hmask, hk, (uint32_t)slot, b.CTR);
+        // Enumerate the perturbed 2-faces uniformly over the group: for each lane
+        // whose word holds zeros (ballot), broadcast that word; key r lands in
+        // lane r, so the stores and table inserts below run one per lane.
+        const uint64_t gmask = G == 64 ? ~0ull : 0xFFFFFFFFull;
+        const int gshift = G == 64 ? 0 : 32 * half;
+        uint64_t myh = 0;
+        uint32_t mypi = 0;
+        int r = 0;
+        for (int it = 0; it * G < Wd; ++it) {
+            const int w = it * G + lane;
+            uint64_t f = 0, zm = 0;
+            if (w < Wd) {
+                const uint64_t lt = lt_mask(w, g.wn, g.bn);
+                f = it == 0 ? f0 : ((Ra[w] | Rb[w]) & lt);
+                zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
+            }
+            uint64_t has = (__ballot(zm != 0ull) >> gshift) & gmask;
+            while (has) {
+                const int src = __builtin_ctzll(has);
+                has &= has - 1;
+                const uint64_t fz = __shfl(f, src, G), zz0 = __shfl(zm, src, G);
+                const int ww = it * G + src;
+                const uint64_t hw = word_hash(ww, fz);
+                uint64_t zz = zz0;
+                while (zz) {
+                    const int bit = __builtin_ctzll(zz);
+                    zz &= zz - 1;
+                    for (int minus = 0; minus < (ww == 0 ? 1 : 2); ++minus) {
+                        if (lane == r) {
+                            myh = hsum - hw + word_hash(ww, fz | ((minus ? 2ull : 1ull) << bit));
+                            mypi = ((uint32_t)ww << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
                         }
+                        ++r;
                     }
-                    ++r;
                 }
+            }
+        }
+        const size_t sbase = (size_t)s * g.P;
+        if (lane < r && lane < g.P) {
+            const size_t slot = sbase + lane;
+            b.PINFO[slot] = mypi;
+            if (g.pair_mode == PAIR_SORT) {
+                b.K32a[slot] = (uint32_t)(myh >> 33);
+                b.FULL[slot] = myh;
+            } else {
+                const uint64_t hk = myh | (1ull << 63);  // never 0 (= empty)
+                b.FULL[slot] = hk;
+                hash_insert(g.HT, g.hmask, hk, (uint32_t)slot, b.CTR);
             }
         }
         for (int rr = ktot + lane; rr < g.P; rr += G) {

@@ -50,6 +50,8 @@ struct StepGeom {
     int j;           // neuron within the layer
     int wn, bn;      // word and bit offset of this neuron's entry
     int P;           // 2-face key slots per split: 2(D-1)
+    int zlo;         // first pre-activation column carried to new vertices: 0, or j + 1 in the
+                     // last subdivided layer (no later evaluation reads the processed columns)
     int pair_mode;   // PAIR_HASH or PAIR_SORT
     uint32_t hmask;  // hash table slots - 1 (PAIR_HASH)
     HEntry *HT;      // this step's hash table (PAIR_HASH)
