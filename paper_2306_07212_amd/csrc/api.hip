@@ -180,6 +180,7 @@ struct Extraction {
             }
             if ((rc = grow_scratch(b.FULL, Kcap, nc))) return rc;
             if ((rc = grow_scratch(b.PINFO, Kcap, nc))) return rc;
+            if (pair_mode == PAIR_HASH && (rc = grow_scratch(b.PART, Kcap, nc))) return rc;
             Kcap = nc;
         }
         if (pair_mode == PAIR_HASH) {

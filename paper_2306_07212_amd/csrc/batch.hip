@@ -83,7 +83,7 @@ __device__ int block_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int 
         int pos = run + wave_off + incl - cnt;
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i)
-            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++);
+            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++, false);
         run += total;
         __syncthreads();
     }

@@ -150,7 +150,12 @@ __device__ __forceinline__ int hash_find(const HEntry *T, uint32_t mask, uint64_
     return -1;
 }
 
-__device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int V0, int nslots, int sa, int sb, size_t out) {
+// Verifies that key slots sa, sb name the same 2-face (their perturbed sign
+// rows agree on every entry before the current neuron) and appends the
+// intersecting edge between their new vertices. check_hash: also compare the
+// stored 64-bit hashes (the hash table already matched them exactly).
+__device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int V0, int nslots, int sa, int sb,
+                                          size_t out, bool check_hash = true) {
     if ((unsigned)sa >= (unsigned)nslots || (unsigned)sb >= (unsigned)nslots) {
         raise_flag(b.CTR, FLAG_BOUNDS);
         return;
@@ -161,14 +166,16 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
     const uint64_t ca = ((pa & 1u) ? 2ull : 1ull) << ((pa >> 1) & 63u);
     const uint64_t cb = ((pb & 1u) ? 2ull : 1ull) << ((pb >> 1) & 63u);
     const uint64_t *Ra = b.SG + (size_t)xa * g.Wd, *Rb = b.SG + (size_t)xb * g.Wd;
-    bool same = b.FULL[sa] == b.FULL[sb];
-    for (int w = 0; w <= g.wn && same; ++w) {
+    uint64_t diff = check_hash ? (b.FULL[sa] ^ b.FULL[sb]) : 0ull;
+    // no early exit: the row loads of all words are independent and pipeline
+#pragma unroll 4
+    for (int w = 0; w <= g.wn; ++w) {
         const uint64_t lt = lt_mask(w, g.wn, g.bn);
         const uint64_t fa = (Ra[w] & lt) | (w == wa ? ca : 0ull);
         const uint64_t fb = (Rb[w] & lt) | (w == wb ? cb : 0ull);
-        same = fa == fb;
+        diff |= fa ^ fb;
     }
-    if (!same) raise_flag(b.CTR, FLAG_VERIFY);
+    if (diff) raise_flag(b.CTR, FLAG_VERIFY);
     int col = kNoCol;
     for (int w = g.wn; w < g.lw1 && col == kNoCol; ++w)
         col = first_col((Ra[w] ^ Rb[w]) & gt_mask(w, g.wn, g.bn, g.lw1), w, g.lw0);
@@ -314,8 +321,8 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
     const double tt = zp / (zp - zq);
     const size_t x0 = (size_t)V0 + s;
     int bad = 0;
-    double Zx[NC];
     uint64_t pb[NC], nb[NC];
+    double *Zo = b.Z + x0 * ZS;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
@@ -323,7 +330,7 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
         const double p = apos ? A[k] : B[k], q = apos ? B[k] : A[k];
         const double z = (c == j) ? 0.0 : p + tt * (q - p);
         if (in && c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
-        Zx[k] = z;
+        if (in && c >= g.zlo) Zo[c] = z;
         pb[k] = __ballot(in && z > 0.0);
         nb[k] = __ballot(in && z < 0.0);
     }
@@ -373,12 +380,6 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
     bad = group_or<G>(bad);
     // ---- stores
     if (lane < D) b.X[x0 * D + lane] = x0c;
-    double *Zo = b.Z + x0 * ZS;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        const int c = k * G + lane;
-        if (c < N && c >= g.zlo) Zo[c] = Zx[k];
-    }
     if (lane < Wd) b.SG[x0 * Wd + lane] = rx0;
     if (lane == 0) {
         if (nz != D - 1 || ktot > g.P) bad |= FLAG_ZERO_COUNT;

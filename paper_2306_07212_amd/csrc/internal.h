@@ -67,6 +67,7 @@ struct Bufs {
     uint32_t *K32a, *K32b, *VALa, *VALb;  // [Kcap] radix-sort ping-pong
     uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot
     uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus
+    int *PART;        // [Kcap] hash pairing: partner slot of an owner slot, else -1
     uint32_t *HIST;   // [256 * tiles]
     int *SELCNT;      // [kSelBlocks] per-chunk match counts of the compaction (also the pairing passes)
     int *CTR;         // [CTR_COUNT]

@@ -425,15 +425,22 @@ __device__ __forceinline__ void pair_chunk(int n, int &c0, int &c1) {
     c1 = min(n, c0 + per);
 }
 
+// Pass 1: every key slot finds its 2-face entry once; PART[u] = the partner
+// slot if u owns the pair (the smaller slot), else -1. Per-chunk owner counts.
 __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g, int nslots) {
     __shared__ int s_w[kThreads / 64];
     int c0, c1;
     pair_chunk(nslots, c0, c1);
     int cnt = 0;
     for (int base = c0 + threadIdx.x * kPairItems; base < c1; base += kThreads * kPairItems)
+#pragma unroll
         for (int i = 0; i < kPairItems; ++i) {
-            int partner;
-            if (base + i < c1 && hash_owner(b, g, base + i, nslots, partner)) ++cnt;
+            const int u = base + i;
+            if (u >= c1) break;
+            int partner = -1;
+            const bool own = hash_owner(b, g, u, nslots, partner);
+            b.PART[u] = own ? partner : -1;
+            cnt += own;
         }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
@@ -445,6 +452,8 @@ __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g, in
     }
 }
 
+// Pass 2: owners in slot order (chunk offsets from pass 1, ordered scatter
+// inside each chunk) append their intersecting edges.
 __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int V0, int E1, int nslots,
                                                           HEntry *clear_t, uint32_t clear_n) {
     __shared__ int s_w[kThreads / 64];
@@ -478,8 +487,10 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int
         int partner[kPairItems];
         uint32_t own = 0;
 #pragma unroll
-        for (int i = 0; i < kPairItems; ++i)
-            if (base + i < c1 && hash_owner(b, g, base + i, nslots, partner[i])) own |= 1u << i;
+        for (int i = 0; i < kPairItems; ++i) {
+            partner[i] = base + i < c1 ? b.PART[base + i] : -1;
+            if (partner[i] >= 0) own |= 1u << i;
+        }
         const int cnt = __popc(own);
         int incl = cnt;
 #pragma unroll
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int
         int pos = run + wave_off + incl - cnt;
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i)
-            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++);
+            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++, false);
         run += total;
     }
 }
