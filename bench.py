@@ -54,8 +54,9 @@ def algorithmic_cost(widths, steps, include_output=False):
     by = dict.fromkeys(FAMILIES, 0.0)
     flops = 0.0
     s0 = 0
-    for ly in layers:
+    for li, ly in enumerate(layers):
         N, K, nw = ly["N"], ly["K"], ly["nw"]
+        last = li == len(layers) - 1
         V0, E0 = steps[s0, 0], steps[s0, 1]
         kin = D if s0 == 0 else K
         flops += 2.0 * V0 * kin * N
@@ -65,9 +66,12 @@ def algorithmic_cost(widths, steps, include_output=False):
             V, E, S, Kv = (float(v) for v in st)
             wn = ly["lw0"] + j // 32  # face sign-vectors span words 0..wn
             by["select"] += 2.0 * E + 4.0 * S
-            # split: read SPL id, edge, two rows (coords, pre-activations, signs), write one row,
-            # two edges, two next-crossings, and 2-face keys (32-bit key per slot, hash + entry per key)
-            by["split"] += S * (4 + 8 + 3 * (8.0 * D + 8.0 * N + 8.0 * Wd) + 16 + 4) + 4.0 * S * P + 12.0 * Kv
+            # split: read SPL id, edge, the two endpoint values at neuron j, two rows (coords, carried
+            # pre-activations, signs), write one row, two edges, two next-crossings, and 2-face keys
+            # (32-bit key per slot, hash + entry per key). Carried columns: all N of the layer (the next
+            # layer's evaluation reads them), in the last subdivided layer only the neurons after j.
+            Nc = (N - j - 1) if last else N
+            by["split"] += S * (4 + 8 + 16 + 3 * (8.0 * D + 8.0 * Nc + 8.0 * Wd) + 16 + 4) + 4.0 * S * P + 12.0 * Kv
             # sort: linear grouping reads and writes each (key, slot) pair once
             by["sort"] += 16.0 * S * P
             # pair: per key its (key, slot) or table entry, hash and perturbed entry; per pair two face
@@ -77,20 +81,65 @@ def algorithmic_cost(widths, steps, include_output=False):
     return by, flops
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["kernels.hip", "device.h", "internal.h"]
+# kernel name prefix -> family (the per-step path's kernels)
+KERNEL_FAMILY = {"pcx::k_gemm": "gemm", "pcx::k_next_all": "next", "pcx::k_sel_": "select",
+                 "pcx::k_split": "split", "pcx::k_sort_": "sort", "pcx::k_pair": "pair", "pcx::k_hpair_": "pair"}
+
+
+def kernels_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2306_07212_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_record(family):
-    """HBM bytes per launch measured with rocprofv3 counters, if they were taken
-    on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    """HBM bytes per launch of a family's kernels measured with rocprofv3 counters,
+    if they were taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2306_07212_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+    rec = json.load(open(TRAFFIC_JSON))
+    if rec.get("kernels_sha256") != kernels_sha256():
         return None
-    return rec.get("families", {}).get(family)
+    fam = rec.get("families", {}).get(family)
+    return None if fam is None else fam["bytes_per_launch"]
 
 
-def cpu_baseline(net, half=0.06):
+def pmc_summary(fetch_csv, write_csv):
+    """Turns two rocprofv3 --pmc runs of `bench.py --copy-probe` (FETCH_SIZE, then
+    WRITE_SIZE) into HBM bytes per launch per kernel family. Each counter is scaled
+    by what it reads for the 1 GiB probe copy (2^30 bytes read, 2^30 written)."""
+    import csv
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        probe = [float(r["Counter_Value"]) for r in rows
+                 if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 2.0 ** 18]
+        if not probe:
+            raise SystemExit(f"{path}: no 1 GiB probe copy found (run bench.py with --copy-probe)")
+        scale = 2.0 ** 30 / (probe[0] * 1024.0)   # bytes per counter KiB
+        per = {}
+        for r in rows:
+            fam = next((f for k, f in KERNEL_FAMILY.items() if r["Kernel_Name"].startswith(k)), None)
+            if fam is None:
+                continue
+            per.setdefault(fam, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
+        return per, scale
+
+    fetch, fs = load(fetch_csv, "FETCH_SIZE")
+    write, ws = load(write_csv, "WRITE_SIZE")
+    fams = {}
+    for f in fetch:
+        fams[f] = {"dispatches": len(fetch[f]), "fetch_bytes_per_launch": sum(fetch[f]) / len(fetch[f]),
+                   "write_bytes_per_launch": sum(write.get(f, [0.0])) / max(1, len(write.get(f, [])))}
+        fams[f]["bytes_per_launch"] = fams[f]["fetch_bytes_per_launch"] + fams[f]["write_bytes_per_launch"]
+    return {"kernels_sha256": kernels_sha256(), "fetch_scale_bytes_per_KiB": fs,
+            "write_scale_bytes_per_KiB": ws, "families": fams}
+
+
+def cpu_baseline(net, half=0.08):
     """The CPU oracle (single thread) on the centred sub-box [-half, half]^3 of
     the same network: a bounded sample of the same workload."""
     import oracle
@@ -126,6 +175,12 @@ def form_batched(args, pcx, wl, torch):
         bt.close()
     torch.cuda.synchronize()
     T = (time.perf_counter() - t0) / args.steps
+    # outside the timed region: one extraction followed by the copy of the complex to host memory
+    t1 = time.perf_counter()
+    cx = run(False)
+    cx.copy()
+    cx.close()
+    T_d2h = time.perf_counter() - t1
     # per-step path on a stratified sample (every 16th network), scaled by splits
     sample = list(range(0, len(nets), 16))
     t1 = time.perf_counter()
@@ -251,8 +306,8 @@ def form_backward(args, pcx, wl, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain_large", help="workloads function name (default: the 768-neuron net)")
     ap.add_argument("--pairing", default="hash", choices=["hash", "sort"], help="step-5 grouping of 2-face keys")
@@ -261,7 +316,16 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 1 GiB device copy (reads 1 GiB, writes 1 GiB): the reference for "
                          "scaling hardware traffic counters")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn the counter CSVs of two rocprofv3 --pmc runs of this script (with "
+                         "--copy-probe) into profiles/traffic.json")
     args = ap.parse_args()
+    if args.pmc_summary:
+        rec = pmc_summary(*args.pmc_summary)
+        rec["sources"] = args.pmc_summary
+        json.dump(rec, open(TRAFFIC_JSON, "w"), indent=1)
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU design is documented, not built)", file=sys.stderr)
@@ -322,6 +386,12 @@ def main():
         cx.close()
     torch.cuda.synchronize()
     T = (time.perf_counter() - t0) / args.steps
+    # outside the timed region: one extraction followed by the copy of the complex to host memory
+    t1 = time.perf_counter()
+    cx = run(False)
+    cx.copy()
+    cx.close()
+    T_d2h = time.perf_counter() - t1
 
     by, flops = algorithmic_cost(net.widths, steps, incl)
     avg_launch_s = dom_ms / 1e3 / max(1, dom_launches)
@@ -334,6 +404,16 @@ def main():
         achieved = by[dom] / per_ext_launches / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS}
+    # every family, from the warm-up's per-family event times (all families timed at once)
+    fam_roof = {}
+    for f in FAMILIES:
+        if fam_ms[f] <= 0:
+            continue
+        s = fam_ms[f] / 1e3
+        fam_roof[f] = {"ms": fam_ms[f], "GB_per_s": by[f] / s / 1e9, "hbm_frac": by[f] / s / 1e9 / HBM_PEAK_GBS}
+        if f == "gemm":
+            fam_roof[f]["TFLOP_per_s"] = flops / s / 1e12
+            fam_roof[f]["alu_frac"] = flops / s / 1e12 / FP64_PEAK_TFLOPS
     roof["traffic"] = traffic_record(dom)
     roof["kernel"] = dom
     roof["launches_per_step"] = per_ext_launches
@@ -358,11 +438,14 @@ def main():
                    "parallelism": "single GPU"},
         "vertices_per_s": info.V / T,
         "edges_per_s": info.E / T,
+        "edge_sign_tests_per_s": float(steps[:, 1].sum()) / T,
+        "ms_with_copy_to_host": T_d2h * 1e3,
         "V": info.V, "E": info.E, "splits": info.total_splits, "pairs": info.total_pairs,
         "peak_device_bytes": info.peak_bytes,
         "device_ms_per_step": info.time_ms,
         "kernel_ms_warmup": fam_ms,
         "roofline": roof,
+        "families": fam_roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(net) if args.workload == "plain_large" else None

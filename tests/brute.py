@@ -240,3 +240,56 @@ def regions_by_perturbation(S, edges, D):
             r[zs] = combo
             regs.add(r.tobytes())
     return regs
+
+
+def arrangement_counts_3d(W, b, lo, hi):
+    """Vertex and edge counts of the 1-skeleton cut out of a 3-D box by the planes
+    W x + b = 0 (one hidden layer), counted directly, for hundreds of planes.
+
+    Vertices: the 8 corners; one per (plane, box edge) crossing; one per (pair of
+    planes, box face) whose intersection line meets the open face; one per triple
+    of planes whose common point lies in the open box. Edges from the degrees:
+    a vertex with z zero box entries has degree 2D - z (Sec. 4.1 at k = 0), so
+    E = (3*8 + 4*n_edge + 5*n_face + 6*n_inner) / 2."""
+    W = np.asarray(W, np.float64)
+    b = np.asarray(b, np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    n = len(b)
+    assert W.shape == (n, 3)
+    n_edge = 0
+    for k in range(3):                       # box edges along axis k
+        o = [a for a in range(3) if a != k]
+        for u in (lo[o[0]], hi[o[0]]):
+            for v in (lo[o[1]], hi[o[1]]):
+                p0 = np.zeros(3)
+                p1 = np.zeros(3)
+                p0[o[0]] = p1[o[0]] = u
+                p0[o[1]] = p1[o[1]] = v
+                p0[k], p1[k] = lo[k], hi[k]
+                z0, z1 = W @ p0 + b, W @ p1 + b
+                n_edge += int(np.sum(z0 * z1 < 0))
+    ii, jj = np.triu_indices(n, 1)
+    n_face = 0
+    for k in range(3):                       # faces x_k = lo_k / hi_k
+        o = [a for a in range(3) if a != k]
+        for c in (lo[k], hi[k]):
+            A = np.stack([W[ii][:, o], W[jj][:, o]], axis=1)          # [P, 2, 2]
+            r = -np.stack([b[ii] + W[ii, k] * c, b[jj] + W[jj, k] * c], axis=1)
+            det = A[:, 0, 0] * A[:, 1, 1] - A[:, 0, 1] * A[:, 1, 0]
+            y0 = (r[:, 0] * A[:, 1, 1] - A[:, 0, 1] * r[:, 1]) / det
+            y1 = (A[:, 0, 0] * r[:, 1] - r[:, 0] * A[:, 1, 0]) / det
+            inside = (y0 > lo[o[0]]) & (y0 < hi[o[0]]) & (y1 > lo[o[1]]) & (y1 < hi[o[1]])
+            n_face += int(np.sum(inside))
+    n_inner = 0
+    for i in range(n - 2):                   # triples i < j < k, one i at a time
+        jk = np.array(list(itertools.combinations(range(i + 1, n), 2)), dtype=np.int64).reshape(-1, 2)
+        if len(jk) == 0:
+            continue
+        A = np.stack([np.broadcast_to(W[i], (len(jk), 3)), W[jk[:, 0]], W[jk[:, 1]]], axis=1)
+        r = -np.stack([np.full(len(jk), b[i]), b[jk[:, 0]], b[jk[:, 1]]], axis=1)
+        x = np.linalg.solve(A, r[..., None])[..., 0]
+        n_inner += int(np.sum(np.all((x > lo) & (x < hi), axis=1)))
+    V = 8 + n_edge + n_face + n_inner
+    E = (3 * 8 + 4 * n_edge + 5 * n_face + 6 * n_inner) // 2
+    return V, E

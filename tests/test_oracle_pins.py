@@ -225,3 +225,30 @@ def test_implicit_gradient_matches_oracle_finite_differences(oracle_lib):
     num = sum(np.sum((a - c) ** 2) for a, c in zip(gW + gb, fW + fb))
     den = sum(np.sum(c ** 2) for c in fW + fb)
     assert np.sqrt(num / den) < 1e-6, np.sqrt(num / den)
+
+
+# ------------------------------------------------- one layer, counted in closed form
+
+def test_arrangement_closed_form_matches_brute_force(oracle_lib):
+    """The direct count of an arrangement's vertices (corners, edge crossings,
+    face lines, triple points) agrees with the D-subset brute force and with
+    the oracle on small single-layer nets."""
+    for seed in (61, 62, 63):
+        net = wl.he_mlp([3, 9, 1], seed)
+        box = wl.cube(3)
+        V, E = brute.arrangement_counts_3d(net.W[0], net.b[0], box.lo, box.hi)
+        Xb, _ = brute.vertices(net, box.lo, box.hi)
+        assert len(Xb) == V
+        r = oracle_lib.extract(net, box.lo, box.hi)
+        assert (r.V, r.E) == (V, E)
+
+
+def test_first_layer_of_768_neuron_workload(oracle_lib):
+    """The first layer of the 3-256-256-256-1 workload (256 planes) alone: the
+    oracle's 1-skeleton has the closed-form vertex and edge counts."""
+    big = wl.plain_large()
+    net = wl.Net([3, 256, 1], [big.W[0], np.zeros((1, 256))], [big.b[0], np.zeros(1)], "layer1")
+    box = wl.cube(3)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    assert (r.V, r.E) == brute.arrangement_counts_3d(net.W[0], net.b[0], box.lo, box.hi) == (1873709, 5588974)
+    assert int(r.steps[:, 2].sum()) == r.V - 8
