@@ -284,22 +284,13 @@ struct GemmLds {
 // -------------------------------------------- steps 4-5a: split and keys
 // The work of one splitting edge s for a group of G lanes (lane = 0..G-1;
 // half = which 32-lane half of the wave the group is, for G = 32).
+// split_core: the split of edge e = ab (already read and bounds-checked)
 template <int G, int NC>
-__device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int lane, int half) {
+__device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int e, int2 ab,
+                                           int lane, int half) {
     constexpr int wpc = G / 32;  // sign words per chunk
     const int D = g.D, Wd = g.Wd, ZS = g.ZS, j = g.j, N = g.Nl;
     const int nw = g.lw1 - g.lw0;
-
-    const int e = b.SPL[s];
-    if ((unsigned)e >= (unsigned)E0) {
-        if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
-        return;
-    }
-    const int2 ab = b.EDG[e];
-    if ((unsigned)ab.x >= (unsigned)V0 || (unsigned)ab.y >= (unsigned)V0) {
-        if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
-        return;
-    }
     const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;
     const uint64_t *Ra = b.SG + (size_t)ab.x * Wd, *Rb = b.SG + (size_t)ab.y * Wd;
     // ---- loads
@@ -446,6 +437,27 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
             else b.FULL[sbase + rr] = 0ull;
         }
     }
+}
+
+// checks of a split-list entry and its edge (out of range: flag, no work)
+__device__ __forceinline__ bool split_entry_ok(const Bufs &b, int e, int E0) { return (unsigned)e < (unsigned)E0; }
+__device__ __forceinline__ bool split_edge_ok(int2 ab, int V0) {
+    return (unsigned)ab.x < (unsigned)V0 && (unsigned)ab.y < (unsigned)V0;
+}
+
+template <int G, int NC>
+__device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int lane, int half) {
+    const int e = b.SPL[s];
+    if (!split_entry_ok(b, e, E0)) {
+        if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
+        return;
+    }
+    const int2 ab = b.EDG[e];
+    if (!split_edge_ok(ab, V0)) {
+        if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
+        return;
+    }
+    split_core<G, NC>(b, g, V0, E0, s, e, ab, lane, half);
 }
 
 }  // namespace pcx

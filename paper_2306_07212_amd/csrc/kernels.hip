@@ -65,9 +65,161 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Bufs b, int ZS, const double 
     gemm_tile(b, ZS, in, in_stride, relu, V, K, N, Wt, bias, Wd, lw0, blockIdx.x * kGemmRows, hs, ws);
 }
 
+// The same evaluation on the matrix cores, for wide layers (N > 128, K >= 16).
+// Wave w owns columns [64 (w%4), +64) of the row band w/4 as RT x 4 tiles of
+// the FP64 16x16x4 MFMA (lane l of a tile holds rows l/16 + 4i, column l%16,
+// i = 0..3). A chain of these MFMAs rounds exactly like the sequential fma
+// chain of k_gemm, so both kernels give identical bits. K advances in chunks
+// of MK staged through LDS (h k-major, W^T row-major); the next chunk's global
+// loads are in flight while the current chunk's MFMAs run, and with DB the LDS
+// is double-buffered (one barrier per chunk). In place as above: a workgroup
+// reads all its rows before the epilogue writes them. Launched with 8 waves
+// of 2 x 4 tiles (64 rows per workgroup, 4 waves per SIMD), MK = 8.
+constexpr int kMPad = 2;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// RT: 16-row tiles per wave; WAVES: waves per workgroup, 4 per 64-row band of
+// column blocks (wave w: columns [64 (w%4), +64), row band w/4).
+template <int MK, int RT, int WAVES, int MINW, bool DB>
+__global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, const double *in, int in_stride,
+                                                                int relu, int V, int K, int N,
+                                                                const double *__restrict__ Wt,
+                                                                const double *__restrict__ bias, int Wd, int lw0) {
+    constexpr int T = 64 * WAVES;
+    constexpr int ROWS = (WAVES / 4) * RT * 16;
+    constexpr int APT = ROWS * MK / T;  // h values staged per thread
+    constexpr int WPT = MK * kMaxWidth / T;  // W^T values staged per thread
+    static_assert(APT >= 1 && MK % APT == 0 && WPT >= 1, "staging map");
+    constexpr int NB = DB ? 2 : 1;
+    __shared__ double as[NB][MK][ROWS + kMPad];
+    __shared__ double ws[NB][MK][kMaxWidth + kMPad];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int v0 = blockIdx.x * ROWS;
+    // staging map: h row t / (MK/APT), k offsets APT (t % (MK/APT)) .. +APT-1;
+    // W^T rows WPT (t / 256) .. +WPT-1, column t % 256
+    const int ar = t / (MK / APT), ak = (t % (MK / APT)) * APT;
+    const int wc = t % kMaxWidth, wk = (t / kMaxWidth) * WPT;
+    const bool arow = v0 + ar < V;
+    const double *arow_p = in + (size_t)(v0 + ar) * in_stride;
+    double pa[APT], pw[WPT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < APT; ++i) {
+            double h = 0.0;
+            if (arow && k0 + ak + i < K) {
+                h = arow_p[k0 + ak + i];
+                if (relu) h = h > 0.0 ? h : 0.0;
+            }
+            pa[i] = h;
+        }
+#pragma unroll
+        for (int i = 0; i < WPT; ++i)
+            pw[i] = (k0 + wk + i < K && wc < N) ? Wt[(size_t)(k0 + wk + i) * N + wc] : 0.0;
+    };
+    dbl4 acc[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int col0 = (w & 3) * 64;
+    const int rb = (w >> 2) * RT * 16;
+    const bool wave_live = col0 < N;
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < APT; ++i) as[buf][ak + i][ar] = pa[i];
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) ws[buf][wk + i][wc] = pw[i];
+    };
+    auto compute = [&](int buf) {
+        if (!wave_live) return;
+#pragma unroll
+        for (int kk = 0; kk < MK; kk += 4) {
+            double af[RT], bf[4];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) af[rt] = as[buf][kk + (l >> 4)][rb + rt * 16 + (l & 15)];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) bf[ct] = ws[buf][kk + (l >> 4)][col0 + ct * 16 + (l & 15)];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+        }
+    };
+    fetch(0);
+    if (DB) {
+        // one barrier per chunk: compute from one buffer while the next chunk is stored into the other
+        put(0);
+        __syncthreads();
+        int c = 0;
+        for (int k0 = 0; k0 < K; k0 += MK, ++c) {
+            const bool more = k0 + MK < K;
+            if (more) fetch(k0 + MK);
+            compute(c & 1);
+            if (more) put((c & 1) ^ 1);
+            __syncthreads();
+        }
+    } else {
+        for (int k0 = 0; k0 < K; k0 += MK) {
+            __syncthreads();
+            put(0);
+            __syncthreads();
+            if (k0 + MK < K) fetch(k0 + MK);
+            compute(0);
+        }
+    }
+    if (!wave_live) return;
+    // epilogue: bias, store, and the layer's sign words (two per wave: columns
+    // col0..col0+31 and col0+32..col0+63, each from two tiles' ballots)
+    const int nwords = (N + 31) >> 5;
+    const int q = l >> 4;
+    int zero = 0;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = v0 + rb + rt * 16 + q + 4 * i;
+            uint64_t pb[4], nb[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const int col = col0 + ct * 16 + (l & 15);
+                const bool ok = v < V && col < N;
+                double z = 0.0;
+                if (ok) {
+                    z = acc[rt][ct][i] + bias[col];
+                    b.Z[(size_t)v * ZS + col] = z;
+                    zero |= (z == 0.0);
+                }
+                pb[ct] = __ballot(ok && z > 0.0);
+                nb[ct] = __ballot(ok && z < 0.0);
+            }
+            // lane 16q + p writes word p (p = 0, 1) of this row
+            const int p = l & 15;
+            if (p < 2 && v < V) {
+                const int word = (col0 >> 5) + p;
+                if (word < nwords) {
+                    const int sh = 16 * q;
+                    const uint32_t pos = (uint32_t)((pb[2 * p] >> sh) & 0xFFFFu) |
+                                         ((uint32_t)((pb[2 * p + 1] >> sh) & 0xFFFFu) << 16);
+                    const uint32_t neg = (uint32_t)((nb[2 * p] >> sh) & 0xFFFFu) |
+                                         ((uint32_t)((nb[2 * p + 1] >> sh) & 0xFFFFu) << 16);
+                    b.SG[(size_t)v * Wd + lw0 + word] = codes_of(pos, neg);
+                }
+            }
+        }
+    }
+    if (zero) raise_flag(b.CTR, FLAG_ZERO_SIGN);
+}
+
 void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int relu, int V, int K, int N,
                  const double *Wt, const double *bias, int Wd, int lw0, hipStream_t st) {
     if (V <= 0) return;
+    if (N > 128 && N <= kMaxWidth && K >= 16) {
+        const int grid = (V + 63) / 64;
+        hipLaunchKernelGGL((k_gemm_mfma<8, 2, 8, 4, false>), dim3(grid), dim3(512), 0, st, b, ZS, in, in_stride, relu, V, K, N, Wt,
+                           bias, Wd, lw0);
+        return;
+    }
     const int grid = (V + kGemmRows - 1) / kGemmRows;
     hipLaunchKernelGGL(k_gemm, dim3(grid), dim3(kThreads), 0, st, b, ZS, in, in_stride, relu, V, K, N, Wt, bias,
                        Wd, lw0);

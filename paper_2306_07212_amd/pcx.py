@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -172,7 +173,9 @@ class MLP:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the library handle (and the HIP runtime) may already be gone
+        if _lib is not None and not sys.is_finalizing():
+            self.close()
 
 
 @dataclass
@@ -265,7 +268,9 @@ class Complex:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the library handle (and the HIP runtime) may already be gone
+        if _lib is not None and not sys.is_finalizing():
+            self.close()
 
 
 def timing_mask(families) -> int:
@@ -365,7 +370,9 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the library handle (and the HIP runtime) may already be gone
+        if _lib is not None and not sys.is_finalizing():
+            self.close()
 
 
 def batch_tune(mlps, boxes, include_output: bool = False) -> int:
@@ -448,4 +455,6 @@ class Server:
             self._keep.clear()
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the library handle (and the HIP runtime) may already be gone
+        if _lib is not None and not sys.is_finalizing():
+            self.close()
