@@ -303,6 +303,49 @@ def form_backward(args, pcx, wl, torch):
             "fp64": res["f64"], "fp32": res["f32"], "fp32_rel_error_vs_fp64": (num / den) ** 0.5}
 
 
+def form_levelset(args, pcx, wl, torch):
+    """Level-set extraction (the output neuron subdivided last) with pruning during
+    subdivision (Sec. 5.4.2) against the full extraction, on the 3-64-64-64-1 and
+    the 3-256-256-256-1 networks."""
+    out = {}
+    for name in ("differentiable", "plain_large"):
+        net = getattr(wl, name)()
+        box = wl.cube(net.D)
+        m = pcx.MLP.from_net(net)
+        res = {}
+        for prune in (False, True):
+            for _ in range(max(1, args.warmup)):
+                pcx.extract(m, box.lo, box.hi, include_output=True, prune=prune).close()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                cx = pcx.extract(m, box.lo, box.hi, include_output=True, prune=prune)
+                inf = cx.info()
+                steps = cx.steps()
+                cx.close()
+            torch.cuda.synchronize()
+            T = (time.perf_counter() - t0) / args.steps
+            starts, s0 = [], 0
+            for n in net.widths[1:]:
+                starts.append([int(steps[s0, 0]), int(steps[s0, 1])])
+                s0 += n
+            res["pruned" if prune else "full"] = {"ms": T * 1e3, "V": inf.V, "E": inf.E,
+                                                  "splits": inf.total_splits, "layer_starts_V_E": starts}
+            print(f"[bench] levelset {name} prune={prune}: {T * 1e3:.1f} ms V={inf.V} E={inf.E}", file=sys.stderr,
+                  flush=True)
+        m.close()
+        res["speedup"] = res["full"]["ms"] / res["pruned"]["ms"]
+        out[name] = res
+    big = out["plain_large"]
+    return {"metric": METRIC, "value": big["pruned"]["splits"] / (big["pruned"]["ms"] / 1e3),
+            "unit": "edges subdivided/s (pruned level-set extraction)", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": big["pruned"]["ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "level set of the output of MLP 3-256-256-256-1 (and 3-64-64-64-1), box [-1,1]^3, "
+                                   "pruning during subdivision vs full extraction", "parallelism": "single GPU"},
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,7 +354,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain_large", help="workloads function name (default: the 768-neuron net)")
     ap.add_argument("--pairing", default="hash", choices=["hash", "sort"], help="step-5 grouping of 2-face keys")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "backward"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "backward", "levelset"],
                     help="plain (default): one large network; the others measure the systems forms")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 1 GiB device copy (reads 1 GiB, writes 1 GiB): the reference for "
@@ -342,7 +385,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.form != "plain":
-        fn = {"batched": form_batched, "served": form_served, "backward": form_backward}[args.form]
+        fn = {"batched": form_batched, "served": form_served, "backward": form_backward,
+              "levelset": form_levelset}[args.form]
         print(json.dumps(fn(args, pcx, wl, torch)), flush=True)
         return
 

@@ -66,7 +66,13 @@ typedef struct {
     uint64_t max_bytes;     /* cap on device bytes the extraction may hold; 0 = no cap */
     void *stream;           /* hipStream_t to run on; NULL = the default stream */
     int32_t batch_wg_per_cu;/* pcx_extract_batch: workgroups per compute unit; 0 = tuned / default */
-    int32_t reserved;
+    int32_t prune;          /* 1 (needs include_output; pcx_extract only, not with record_tape): pruning
+                               during subdivision for level-set extraction (Sec. 5.4.2). Before each
+                               subdivided layer, edges whose two vertices agree in sign on every neuron
+                               still to come (the output included) are dropped, then vertices left
+                               without edges; survivors keep their order. The result holds the whole
+                               output level set and the cells pruning could not exclude; the per-step
+                               counters show the pruned sizes at each layer start. */
 } pcx_opts;
 
 /* Summary of an extracted complex. */

@@ -73,6 +73,7 @@ struct Extraction {
     uint32_t Tused[2] = {0, 0};          // entries a step left to clear
     int hparity = 0;
     bool tape = false;
+    bool prune = false;
     int D = 0, Wd = 0, ZS = 0, P = 0;
     int *hctr = nullptr;  // pinned
     EventPool ev;
@@ -206,6 +207,86 @@ struct Extraction {
     }
 };
 
+int degenerate_message(int flags);
+
+// Pruning (Sec. 5.4.2): the signs of the neurons of the later layers (the
+// output included) at every current vertex, written into their sign words by
+// the evaluation, in chunks of rows through two scratch buffers.
+int future_signs(Extraction &x, const pcx_mlp *mlp, int l, int nsub, int64_t V, const std::vector<int> &lw) {
+    if (l + 1 >= nsub || V == 0) return PCX_OK;
+    const int ZS = x.ZS, Wd = x.Wd;
+    const int64_t chunk = std::min<int64_t>(V, 1 << 20);
+    void *q[2];
+    int rc;
+    if ((rc = x.arena.alloc(&q[0], (size_t)chunk * ZS * sizeof(double)))) return rc;
+    if ((rc = x.arena.alloc(&q[1], (size_t)chunk * ZS * sizeof(double)))) return rc;
+    for (int64_t c0 = 0; c0 < V; c0 += chunk) {
+        const int n = (int)std::min(chunk, V - c0);
+        const double *src = x.b.Z + (size_t)c0 * ZS;
+        for (int m = l + 1; m < nsub; ++m) {
+            Bufs bb = x.b;
+            bb.Z = (double *)q[m & 1];
+            bb.SG = x.b.SG + (size_t)c0 * Wd;
+            launch_gemm(bb, ZS, src, ZS, 1, n, mlp->widths[m], mlp->widths[m + 1], mlp->Wt[m], mlp->b[m], Wd, lw[m],
+                        x.st);
+            src = bb.Z;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(x.st));
+    x.arena.release(q[0]);
+    x.arena.release(q[1]);
+    return PCX_OK;
+}
+
+// Drop the edges whose vertices agree on every sign word from lwf on, then the
+// vertices left without an edge; survivors keep their order.
+int prune_now(Extraction &x, int64_t &V, int64_t &E, int lwf, int64_t &E_before) {
+    E_before = E;
+    if (V == 0) return PCX_OK;
+    hipStream_t st = x.st;
+    void *pm, *pmap, *pe, *px, *ps, *pz;
+    int rc;
+    // the host learns the edge count only at each step's compaction: take the
+    // count the last step's pairing left on the device
+    HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
+    E = x.hctr[CTR_E];
+    E_before = E;
+    if ((rc = x.arena.alloc(&pm, (size_t)V))) return rc;
+    if ((rc = x.arena.alloc(&pmap, (size_t)V * sizeof(int)))) return rc;
+    if ((rc = x.arena.alloc(&pe, x.Ecap * sizeof(int2)))) return rc;
+    HIPCHK(hipMemsetAsync(pm, 0, (size_t)V, st));
+    launch_prune_edges(x.b, (int)V, (int)E, x.Wd, lwf, (int2 *)pe, (uint8_t *)pm, st);
+    launch_prune_vertices(x.b, (int)V, (const uint8_t *)pm, (int *)pmap, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
+    const int64_t Vn = x.hctr[CTR_V], En = x.hctr[CTR_E];
+    if ((rc = x.arena.alloc(&px, x.Vcap * (size_t)x.D * sizeof(double)))) return rc;
+    if ((rc = x.arena.alloc(&ps, x.Vcap * (size_t)x.Wd * sizeof(uint64_t)))) return rc;
+    if ((rc = x.arena.alloc(&pz, x.Vcap * (size_t)x.ZS * sizeof(double)))) return rc;
+    launch_move_rows(x.b, (const uint8_t *)pm, (const int *)pmap, (int)V, x.D, x.Wd, x.ZS, (double *)px,
+                     (uint64_t *)ps, (double *)pz, (int2 *)pe, (int)En, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    x.arena.release(x.b.X);
+    x.arena.release(x.b.SG);
+    x.arena.release(x.b.Z);
+    x.arena.release(x.b.EDG);
+    x.arena.release(pm);
+    x.arena.release(pmap);
+    x.b.X = (double *)px;
+    x.b.SG = (uint64_t *)ps;
+    x.b.Z = (double *)pz;
+    x.b.EDG = (int2 *)pe;
+    V = Vn;
+    E = En;
+    return PCX_OK;
+}
+
 int degenerate_message(int flags) {
     std::string m = "input is not generic:";
     if (flags & FLAG_ZERO_SIGN) m += " a vertex lies on a hyperplane;";
@@ -317,6 +398,9 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     if (o.pairing != PCX_PAIR_HASH && o.pairing != PCX_PAIR_SORT) return fail(PCX_ERR_INVALID, "unknown pairing");
     x.pair_mode = o.pairing == PCX_PAIR_SORT ? PAIR_SORT : PAIR_HASH;
     x.tape = o.record_tape != 0;
+    x.prune = o.prune != 0;
+    if (x.prune && !o.include_output) return fail(PCX_ERR_INVALID, "pruning needs include_output (the level set)");
+    if (x.prune && x.tape) return fail(PCX_ERR_INVALID, "pruning and record_tape cannot be combined");
     std::vector<double *> tapeZ;
     hipStream_t st = x.st;
     int rc;
@@ -373,6 +457,7 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     std::vector<int64_t> steps((size_t)n_steps * 4, 0);
     int64_t V = (int64_t)V0, E = (int64_t)E0;
     int64_t prevE = -1, prevS = 0;
+    bool k_recorded = false;  // the previous step's pair count was taken before a pruning
     int step = 0;
     int64_t total_splits = 0;
     const char *verbose_env = getenv("PCX_VERBOSE");
@@ -400,6 +485,18 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
             launch_gemm(x.b, ZS, x.b.Z, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
         }
         if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
+        if (x.prune) {
+            if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
+            if ((rc = future_signs(x, mlp, l, nsub, V, lw))) return rc;
+            if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
+            if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
+            int64_t Epre = E;
+            if ((rc = prune_now(x, V, E, lw[l], Epre))) return rc;
+            // the previous step's pair count, from the edge count before pruning
+            if (step > 0) steps[(size_t)(step - 1) * 4 + 3] = 2 * (Epre - prevE - prevS);
+            k_recorded = true;
+            if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
+        }
         if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
         launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, st);
         if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
@@ -415,7 +512,8 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
             if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
             const int64_t S = x.hctr[CTR_S];
             E = x.hctr[CTR_E];
-            if (step > 0) steps[(size_t)(step - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+            if (step > 0 && !k_recorded) steps[(size_t)(step - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+            k_recorded = false;
             steps[(size_t)step * 4 + 0] = V;
             steps[(size_t)step * 4 + 1] = E;
             steps[(size_t)step * 4 + 2] = S;

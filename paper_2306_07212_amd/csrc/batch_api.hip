@@ -39,6 +39,7 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
     if (n < 0 || (n > 0 && (!mlps || !lo || !hi))) return fail(PCX_ERR_INVALID, "NULL argument");
     pcx_opts o{};
     if (opts) o = *opts;
+    if (o.prune || o.record_tape) return fail(PCX_ERR_INVALID, "batched extraction supports neither prune nor record_tape");
     hipStream_t st = (hipStream_t)o.stream;
     auto t_start = std::chrono::steady_clock::now();
     auto *bt = new pcx_batch();

@@ -327,17 +327,33 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     }
     const double xp = apos ? xa : xb, xq = apos ? xb : xa;
     const double x0c = xp + tt * (xq - xp);
-    // ---- sign row of x0, hash of the edge's sign-vector, zeros, next crossings
-    uint64_t hsum = 0, rx0 = 0, f0 = 0;
-    int nz = 0, nkeys = 0, da = kNoCol, db = kNoCol;
-    for (int w = lane, it = 0; w < Wd; w += G, ++it) {
-        const uint64_t wa = it == 0 ? wa0 : Ra[w], wb = it == 0 ? wb0 : Rb[w];
-        const uint64_t lt = lt_mask(w, g.wn, g.bn), gt = gt_mask(w, g.wn, g.bn, g.lw1);
+    // ---- sign row of x0, hash of the edge's sign-vector, zeros, next crossings.
+    // The loop runs uniformly over the group; lane c of iteration it owns word
+    // it*G + c. Zero entries are few (D-1), so their counts travel by ballot:
+    // every zero of the edge's sign-vector gives the 2-faces of step 5 (one for
+    // a box entry, two for a neuron, in word, bit, sign order), and key r is
+    // built by lane r, which here learns the word that holds it.
+    const uint64_t gmask = G == 64 ? ~0ull : 0xFFFFFFFFull;
+    const int gshift = G == 64 ? 0 : 32 * half;
+    uint64_t hsum = 0, rx0 = 0;
+    uint64_t kf = 0, kz = 0;  // for key `lane`: the edge's sign word and its zeros there
+    int kw = -1, kli = 0;     //                 that word's index, the key's rank inside the word
+    int nz = 0, ktot = 0, da = kNoCol, db = kNoCol;
+    for (int it = 0; it * G < Wd; ++it) {
+        const int w = it * G + lane;
+        const bool live = w < Wd;
+        uint64_t wa = 0, wb = 0;
+        if (live) {
+            wa = it == 0 ? wa0 : Ra[w];
+            wb = it == 0 ? wb0 : Rb[w];
+        }
+        const uint64_t lt = live ? lt_mask(w, g.wn, g.bn) : 0ull;
+        const uint64_t gt = live ? gt_mask(w, g.wn, g.bn, g.lw1) : 0ull;
         const uint64_t f = (wa | wb) & lt;
         if (f & (f >> 1) & 0x5555555555555555ull) bad |= FLAG_CONFLICT;
         uint64_t cw = 0;
         const int u = w - g.lw0;
-        if (u >= 0 && u < nw) {
+        if (live && u >= 0 && u < nw) {
             const int ku = u / wpc, sh = 32 * (wpc == 2 ? (u & 1) : half);
             uint64_t P = 0, Q = 0;
 #pragma unroll
@@ -349,26 +365,46 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
             cw = codes_of((uint32_t)(P >> sh), (uint32_t)(Q >> sh));
         }
         const uint64_t rx = f | (cw & gt);
-        if (it == 0) {
-            rx0 = rx;
-            f0 = f;
-        } else {
-            b.SG[x0 * Wd + w] = rx;
-        }
-        if (w <= g.wn) hsum += word_hash(w, f);
-        const uint64_t zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
+        if (it == 0) rx0 = rx;
+        else if (live) b.SG[x0 * Wd + w] = rx;
+        if (live && w <= g.wn) hsum += word_hash(w, f);
+        const uint64_t zm = live ? (~(f | (f >> 1)) & b.VALID[w] & lt) : 0ull;
         const int zc = __popcll(zm);
-        nz += zc;
-        nkeys += (w == 0) ? zc : 2 * zc;  // box entries all live in word 0
-        da = min(da, first_col((wa ^ rx) & gt, w, g.lw0));
-        db = min(db, first_col((rx ^ wb) & gt, w, g.lw0));
+        uint64_t has = (__ballot(zc != 0) >> gshift) & gmask;
+        int srcl = lane;
+        bool mine = false;
+        while (has) {
+            const int sl = __builtin_ctzll(has);
+            has &= has - 1;
+            const int c = __shfl(zc, sl, G);
+            const int keys = (it == 0 && sl == 0) ? c : 2 * c;  // box entries all live in word 0
+            if (lane >= ktot && lane < ktot + keys) {
+                srcl = sl;
+                kli = lane - ktot;
+                mine = true;
+            }
+            nz += c;
+            ktot += keys;
+        }
+        const uint64_t fz = __shfl(f, srcl, G), zz = __shfl(zm, srcl, G);
+        if (mine) {
+            kf = fz;
+            kz = zz;
+            kw = it * G + srcl;
+        }
+        // the first crossing after j: columns grow with the word, so it sits in the first lane that has one
+        const int cda = first_col((wa ^ rx) & gt, w, g.lw0), cdb = first_col((rx ^ wb) & gt, w, g.lw0);
+        if (da == kNoCol) {
+            const uint64_t m = (__ballot(cda != kNoCol) >> gshift) & gmask;
+            if (m) da = __shfl(cda, __builtin_ctzll(m), G);
+        }
+        if (db == kNoCol) {
+            const uint64_t m = (__ballot(cdb != kNoCol) >> gshift) & gmask;
+            if (m) db = __shfl(cdb, __builtin_ctzll(m), G);
+        }
     }
     hsum = group_sum<G>(hsum);
-    nz = group_sum<G>(nz);
-    const int ktot = group_sum<G>(nkeys);
-    da = group_min<G>(da);
-    db = group_min<G>(db);
-    bad = group_or<G>(bad);
+    if ((__ballot(bad != 0) >> gshift) & gmask) bad = group_or<G>(bad);
     // ---- stores
     if (lane < D) b.X[x0 * D + lane] = x0c;
     if (lane < Wd) b.SG[x0 * Wd + lane] = rx0;
@@ -382,47 +418,16 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         if (b.PQ) b.PQ[x0] = apos ? ab : make_int2(ab.y, ab.x);
     }
     if (g.P > 0) {
-        // Enumerate the perturbed 2-faces uniformly over the group: for each lane
-        // whose word holds zeros (ballot), broadcast that word; key r lands in
-        // lane r, so the stores and table inserts below run one per lane.
-        const uint64_t gmask = G == 64 ? ~0ull : 0xFFFFFFFFull;
-        const int gshift = G == 64 ? 0 : 32 * half;
-        uint64_t myh = 0;
-        uint32_t mypi = 0;
-        int r = 0;
-        for (int it = 0; it * G < Wd; ++it) {
-            const int w = it * G + lane;
-            uint64_t f = 0, zm = 0;
-            if (w < Wd) {
-                const uint64_t lt = lt_mask(w, g.wn, g.bn);
-                f = it == 0 ? f0 : ((Ra[w] | Rb[w]) & lt);
-                zm = ~(f | (f >> 1)) & b.VALID[w] & lt;
-            }
-            uint64_t has = (__ballot(zm != 0ull) >> gshift) & gmask;
-            while (has) {
-                const int src = __builtin_ctzll(has);
-                has &= has - 1;
-                const uint64_t fz = __shfl(f, src, G), zz0 = __shfl(zm, src, G);
-                const int ww = it * G + src;
-                const uint64_t hw = word_hash(ww, fz);
-                uint64_t zz = zz0;
-                while (zz) {
-                    const int bit = __builtin_ctzll(zz);
-                    zz &= zz - 1;
-                    for (int minus = 0; minus < (ww == 0 ? 1 : 2); ++minus) {
-                        if (lane == r) {
-                            myh = hsum - hw + word_hash(ww, fz | ((minus ? 2ull : 1ull) << bit));
-                            mypi = ((uint32_t)ww << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
-                        }
-                        ++r;
-                    }
-                }
-            }
-        }
         const size_t sbase = (size_t)s * g.P;
-        if (lane < r && lane < g.P) {
+        if (lane < ktot && lane < g.P && kw >= 0) {
+            // the key's zero: bit rank kli (box word) or kli/2 with sign kli%2 (neuron words)
+            const int minus = kw == 0 ? 0 : (kli & 1);
+            uint64_t z = kz;
+            for (int k = kw == 0 ? kli : (kli >> 1); k > 0; --k) z &= z - 1;
+            const int bit = __builtin_ctzll(z);
+            const uint64_t myh = hsum - word_hash(kw, kf) + word_hash(kw, kf | ((minus ? 2ull : 1ull) << bit));
             const size_t slot = sbase + lane;
-            b.PINFO[slot] = mypi;
+            b.PINFO[slot] = ((uint32_t)kw << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
             if (g.pair_mode == PAIR_SORT) {
                 b.K32a[slot] = (uint32_t)(myh >> 33);
                 b.FULL[slot] = myh;

@@ -20,7 +20,7 @@ constexpr int kGemmK = 16;               // K-chunk staged in LDS
 constexpr int kMaxWidth = 256;           // widest layer the in-place GEMM handles
 
 // device counters (int32 slots of one small array)
-enum { CTR_S = 0, CTR_KVALID = 1, CTR_E = 2, CTR_FLAGS = 3, CTR_COUNT = 8 };
+enum { CTR_S = 0, CTR_KVALID = 1, CTR_E = 2, CTR_FLAGS = 3, CTR_V = 4, CTR_COUNT = 8 };
 
 // degeneracy / failure flags (bitwise)
 enum : int {
@@ -82,6 +82,12 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
 void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ecap_hint, hipStream_t st);
 void launch_select(const Bufs &b, uint16_t target, hipStream_t st);
 void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st);
+// pruning during subdivision (prune.hip): kept edges -> out (count in CTR_E), their endpoints marked;
+// then marked vertices numbered in order (count in CTR_V); then rows moved and edges renumbered
+void launch_prune_edges(const Bufs &b, int V, int E, int Wd, int lwf, int2 *out, uint8_t *mark, hipStream_t st);
+void launch_prune_vertices(const Bufs &b, int V, const uint8_t *mark, int *map, hipStream_t st);
+void launch_move_rows(const Bufs &b, const uint8_t *mark, const int *map, int V, int D, int Wd, int ZS, double *X2,
+                      uint64_t *SG2, double *Z2, int2 *E2, int Enew, hipStream_t st);
 void launch_sort(const Bufs &b, int n, hipStream_t st);  // result in K32a/VALa
 void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st);
 // hash pairing: count + ordered emit over the key slots; the emit also clears

@@ -44,7 +44,7 @@ class PcxError(RuntimeError):
 class _Opts(C.Structure):
     _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("pairing", C.c_int32),
                 ("record_tape", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p),
-                ("batch_wg_per_cu", C.c_int32), ("reserved", C.c_int32)]
+                ("batch_wg_per_cu", C.c_int32), ("prune", C.c_int32)]
 
 
 class _BatchStats(C.Structure):
@@ -292,14 +292,16 @@ def backward(mlp: MLP, cx: Complex, grad_coords_ptr: int, gW_ptrs, gb_ptrs, prec
 
 
 def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=None,
-            max_bytes: int = 0, pairing: str = "hash", record_tape: bool = False) -> Complex:
-    """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron."""
+            max_bytes: int = 0, pairing: str = "hash", record_tape: bool = False, prune: bool = False) -> Complex:
+    """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron.
+    ``prune`` (with ``include_output``): pruning during subdivision for the output's level set."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
     tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
-    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream, 0, 0)
+    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream, 0,
+              int(bool(prune)))
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))

@@ -127,3 +127,16 @@ def digest(S, edges):
     h.update(np.ascontiguousarray(Sc, np.int8).tobytes())
     h.update(np.ascontiguousarray(Ec, np.int64).tobytes())
     return h.hexdigest()
+
+
+def level_set(X, S, edges):
+    """The output's zero level set inside a complex extracted with the output
+    subdivided: vertices with 0 at the last entry, edges between two of them
+    (renumbered in vertex order)."""
+    keep = np.asarray(S)[:, -1] == 0
+    idx = np.nonzero(keep)[0]
+    new = -np.ones(len(keep), np.int64)
+    new[idx] = np.arange(len(idx))
+    edges = np.asarray(edges, np.int64)
+    both = keep[edges[:, 0]] & keep[edges[:, 1]] if len(edges) else np.zeros(0, bool)
+    return X[idx], S[idx], new[edges[both]].reshape(-1, 2)

@@ -252,3 +252,66 @@ def test_first_layer_of_768_neuron_workload(oracle_lib):
     r = oracle_lib.extract(net, box.lo, box.hi)
     assert (r.V, r.E) == brute.arrangement_counts_3d(net.W[0], net.b[0], box.lo, box.hi) == (1873709, 5588974)
     assert int(r.steps[:, 2].sum()) == r.V - 8
+
+
+# ------------------------------------------------- pruning during subdivision (Sec. 5.4.2)
+
+PRUNE_CASES = [([2, 8, 8, 1], 1), ([3, 8, 8, 1], 5), ([2, 16, 16, 16, 1], 7), ([2, 12, 10, 1], 31),
+               ([3, 10, 10, 10, 1], 32), ([1, 6, 6, 1], 33), ([4, 6, 6, 1], 34)]
+
+
+@pytest.mark.parametrize("widths,seed", PRUNE_CASES)
+def test_pruning_keeps_the_level_set(oracle_lib, widths, seed):
+    """Pruning is sufficient (an edge whose vertices agree on every later neuron
+    is never split and never meets the output's zero set), so the level set of
+    the pruned extraction is the full extraction's, point for point."""
+    from checks import level_set
+    net = wl.he_mlp(widths, seed)
+    box = wl.cube(widths[0])
+    full = oracle_lib.extract(net, box.lo, box.hi, include_output=True)
+    pr = oracle_lib.extract(net, box.lo, box.hi, include_output=True, prune=True)
+    assert_same_complex(level_set(pr.X, pr.S, pr.edges), level_set(full.X, full.S, full.edges), coord_tol=0.0)
+    assert pr.V <= full.V and pr.E <= full.E
+    # every layer starts from a subset of the unpruned complex
+    s0 = 0
+    for n in widths[1:]:
+        assert pr.steps[s0, 0] <= full.steps[s0, 0] and pr.steps[s0, 1] <= full.steps[s0, 1]
+        s0 += n
+
+
+def test_pruning_removes_what_cannot_split(oracle_lib):
+    """On the 3-64-64-64-1 workload the pruned complex is far smaller than the
+    full one, and every pruned layer start keeps only edges that still differ
+    on a later neuron."""
+    net = wl.differentiable()
+    box = wl.cube(3)
+    pr = oracle_lib.extract(net, box.lo, box.hi, include_output=True, prune=True)
+    full_V = 670310
+    assert 0 < pr.V < full_V // 10
+    # the last step (the output neuron) splits exactly the edges left at its start
+    assert pr.steps[-1, 2] == pr.steps[-1, 1]
+
+
+def test_pruning_mistake_is_caught(oracle_lib):
+    """Comparing only the current layer's neurons (mutation 6) prunes edges a
+    later layer would split: the level set changes on some case."""
+    from checks import level_set
+    changed = False
+    for widths, seed in PRUNE_CASES:
+        net = wl.he_mlp(widths, seed)
+        box = wl.cube(widths[0])
+        full = oracle_lib.extract(net, box.lo, box.hi, include_output=True)
+        try:
+            bad = oracle_lib.extract(net, box.lo, box.hi, include_output=True, prune=True, mutation=6)
+            assert_same_complex(level_set(bad.X, bad.S, bad.edges), level_set(full.X, full.S, full.edges),
+                                coord_tol=0.0)
+        except (AssertionError, oracle_lib.OracleError):
+            changed = True  # a different level set, or a splitting 2-face whose partner edge was dropped
+    assert changed
+
+
+def test_pruning_needs_the_output(oracle_lib):
+    net = wl.he_mlp([2, 4, 1], 3)
+    box = wl.cube(2)
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.extract(net, box.lo, box.hi, include_output=False, prune=True)
