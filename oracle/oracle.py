@@ -53,7 +53,8 @@ def _load():
     lib = C.CDLL(_LIB)
     vp = C.c_void_p
     lib.pcxo_extract.restype = vp
-    lib.pcxo_extract.argtypes = [C.POINTER(_Net), C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_int]
+    lib.pcxo_extract.argtypes = [C.POINTER(_Net), C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_int,
+                                 C.c_int]
     lib.pcxo_free.argtypes = [vp]
     for name, rt in [("pcxo_status", C.c_int), ("pcxo_V", C.c_long), ("pcxo_E", C.c_long),
                      ("pcxo_M", C.c_int), ("pcxo_n_steps", C.c_int), ("pcxo_min_margin", C.c_double)]:
@@ -112,13 +113,15 @@ class OracleResult:
         return self.edges.shape[0]
 
 
-def extract(net, lo, hi, include_output: bool = False, mutation: int = 0) -> OracleResult:
-    """Edge subdivision of ``net`` on the box [lo, hi] (float64, single thread)."""
+def extract(net, lo, hi, include_output: bool = False, mutation: int = 0, prune: bool = False) -> OracleResult:
+    """Edge subdivision of ``net`` on the box [lo, hi] (float64, single thread).
+    ``prune`` (with ``include_output``): drop, before each layer, the edges whose
+    vertices agree on every neuron still to come (Sec. 5.4.2)."""
     lib = _load()
     h = _NetHolder(net.widths, net.W, net.b)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
-    r = lib.pcxo_extract(C.byref(h.c), _dp(lo), _dp(hi), int(bool(include_output)), int(mutation))
+    r = lib.pcxo_extract(C.byref(h.c), _dp(lo), _dp(hi), int(bool(include_output)), int(bool(prune)), int(mutation))
     if not r:
         raise MemoryError("oracle allocation failed")
     try:

@@ -11,9 +11,11 @@
  *  - Layers follow Sec. 3.4: x^(l) = ReLU(W^(l) x^(l-1) + b^(l)), with W^(l)
  *    stored row-major as [N_l][N_{l-1}] (z = W x + b).
  *  - Sign of a neuron at x is sgn(z) (Sec. 3.4): + iff z > 0.
- *  - The domain is the box [lo, hi]^D given as 2D half-spaces (Sec. 4.1):
- *    entry 2j is x_j - lo_j >= 0, entry 2j+1 is hi_j - x_j >= 0. They are the
- *    first m = 2D entries of every sign-vector; interior cells are + there.
+ *  - The domain is a bounded polyhedron given as m half-spaces (Sec. 4.1): the
+ *    box [lo, hi]^D (m = 2D; entry 2j is x_j - lo_j >= 0, entry 2j+1 is
+ *    hi_j - x_j >= 0) or a simplex (m = D + 1; entry i is the barycentric
+ *    coordinate of corner i). They are the first m entries of every
+ *    sign-vector; interior cells are + there.
  *  - Then one entry per subdivided neuron, layer by layer in index order.
  *    Hidden neurons are always subdivided; the output layer only when
  *    include_output is set (zero level set of the output, Sec. 5.4).
@@ -62,6 +64,12 @@ static void *xrealloc(void *p, size_t n) {
 
 static int n_sub_layers(const pcxo_net *net, int include_output) {
     return include_output ? net->L : net->L - 1;
+}
+
+static int entry_count_m(const pcxo_net *net, int m, int include_output) {
+    int M = m;
+    for (int l = 1; l <= n_sub_layers(net, include_output); ++l) M += net->widths[l];
+    return M;
 }
 
 static int entry_count(const pcxo_net *net, int include_output) {
@@ -160,22 +168,77 @@ static void fail(pcxo_result *r, int code, const char *msg) {
     snprintf(r->msg, sizeof r->msg, "%s", msg);
 }
 
+/* Pruning during subdivision (Sec. 5.4.2), applied before each subdivided
+ * layer l: the sign of every neuron still to come (layers l..L, the output
+ * included) is taken at every current vertex by the forward pass; an edge
+ * whose two vertices agree on all of them can never split again nor meet the
+ * output's zero level set, so it is dropped, and so are vertices left without
+ * edges. Survivors keep their relative order. Only meaningful for the level
+ * set, so it requires include_output. Returns the new vertex count. */
+static long prune_complex(const pcxo_net *net, int l, int mutation, double *X, int8_t *S, int M,
+                          int32_t *Ed, long V, long *E_io, int *status) {
+    const int D = net->D;
+    int total = 0, first = 0;
+    for (int m = 1; m <= net->L; ++m) {
+        if (m < l) first += net->widths[m];
+        total += net->widths[m];
+    }
+    int last = total;                         /* future neurons: [first, last) of the forward pass */
+    if (mutation == 6) last = first + net->widths[l];  /* planted mistake: current layer only */
+    const int nf = last - first;
+    int8_t *fs = (int8_t *)malloc((size_t)(V ? V : 1) * (size_t)(nf ? nf : 1));
+    double *z = (double *)malloc(sizeof(double) * (size_t)total);
+    long *map = (long *)malloc(sizeof(long) * (size_t)(V ? V : 1));
+    if (!fs || !z || !map) { free(fs); free(z); free(map); *status = PCXO_ERR_OOM; return V; }
+    for (long v = 0; v < V; ++v) {
+        if (pcxo_forward(net, X + v * D, z) != PCXO_OK) { *status = PCXO_ERR_OOM; break; }
+        for (int k = 0; k < nf; ++k) {
+            double zk = z[first + k];
+            fs[v * nf + k] = (int8_t)(zk > 0.0 ? 1 : (zk < 0.0 ? -1 : 0));
+        }
+        map[v] = -1;
+    }
+    long E = *E_io, ne = 0;
+    for (long e = 0; e < E && *status == PCXO_OK; ++e) {
+        int32_t a = Ed[2 * e], b = Ed[2 * e + 1];
+        if (memcmp(fs + (long)a * nf, fs + (long)b * nf, (size_t)nf) == 0) continue;
+        Ed[2 * ne] = a; Ed[2 * ne + 1] = b; ++ne;
+        map[a] = 0; map[b] = 0;
+    }
+    long nv = 0;
+    for (long v = 0; v < V; ++v) {
+        if (map[v] < 0) continue;
+        if (nv != v) {
+            memmove(X + nv * D, X + v * D, sizeof(double) * (size_t)D);
+            memmove(S + nv * M, S + v * M, (size_t)M);
+        }
+        map[v] = nv++;
+    }
+    for (long e = 0; e < ne; ++e) { Ed[2 * e] = (int32_t)map[Ed[2 * e]]; Ed[2 * e + 1] = (int32_t)map[Ed[2 * e + 1]]; }
+    *E_io = ne;
+    free(fs); free(z); free(map);
+    return nv;
+}
+
 /* mutation (test-only planted mistakes; 0 = none):
  *   1: perturb neuron zeros only toward + (drops half of the parent 2-faces)
  *   2: interpolate with the wrong weight, x0 = x_p + (1-t)(x_q - x_p)
  *   3: forget to append the intersecting edges of step 5
  *   4: new vertices inherit the sign of V+ instead of the join
- *   5: step 1 reads the bias of the neighbouring neuron (an index slip) */
-pcxo_result *pcxo_extract(const pcxo_net *net, const double *lo, const double *hi,
-                          int include_output, int mutation) {
+ *   5: step 1 reads the bias of the neighbouring neuron (an index slip)
+ *   6: pruning compares only the current layer's neurons */
+/* The domain (Sec. 4.1) is given by m half-spaces, the first m entries of every
+ * sign-vector, and by its 1-skeleton: nv vertices X0 [nv][D] with their domain
+ * entries S0 [nv][m] (+1 or 0) and ne edges E0 [ne][2]. */
+static pcxo_result *extract_core(const pcxo_net *net, int m, long nv, const double *X0, const int8_t *S0, long ne,
+                                 const int32_t *E0, int include_output, int prune, int mutation) {
     pcxo_result *r = (pcxo_result *)calloc(1, sizeof(pcxo_result));
     if (!r) return NULL;
     const int D = net->D;
     if (D < 1 || D > 20 || net->L < 1 || net->widths[0] != D) { fail(r, PCXO_ERR_INVALID, "bad widths"); return r; }
-    for (int j = 0; j < D; ++j)
-        if (!(lo[j] < hi[j])) { fail(r, PCXO_ERR_INVALID, "empty box"); return r; }
+    if (prune && !include_output) { fail(r, PCXO_ERR_INVALID, "pruning needs the output level set"); return r; }
     const int nsub = n_sub_layers(net, include_output);
-    const int M = entry_count(net, include_output);
+    const int M = entry_count_m(net, m, include_output);
     r->D = D; r->M = M;
     int maxw = D;
     for (int l = 0; l <= net->L; ++l) if (net->widths[l] > maxw) maxw = net->widths[l];
@@ -185,29 +248,16 @@ pcxo_result *pcxo_extract(const pcxo_net *net, const double *lo, const double *h
     r->steps = (long *)calloc((size_t)nsteps * 4 + 1, sizeof(long));
     r->min_margin = INFINITY;
 
-    /* Step 0 (Sec. 4.2.1 with the domain of Sec. 4.1): the 1-skeleton of the
-     * box. Corner c has x_j = hi_j if bit j of c is set, else lo_j; corners at
-     * Hamming distance one share an edge. */
-    long V = 1L << D, E = (long)D << (D - 1);
+    /* Step 0 (Sec. 4.2.1): the 1-skeleton of the domain */
+    long V = nv, E = ne;
     long capV = V < 1024 ? 1024 : V, capE = E < 1024 ? 1024 : E;
     double *X = (double *)malloc(sizeof(double) * (size_t)capV * D);
     int8_t *S = (int8_t *)calloc((size_t)capV * M, 1);
     int32_t *Ed = (int32_t *)malloc(sizeof(int32_t) * (size_t)capE * 2);
     if (!X || !S || !Ed) { free(X); free(S); free(Ed); fail(r, PCXO_ERR_OOM, "oom"); return r; }
-    for (long c = 0; c < V; ++c) {
-        for (int j = 0; j < D; ++j) {
-            int up = (int)((c >> j) & 1);
-            X[c * D + j] = up ? hi[j] : lo[j];
-            S[c * M + 2 * j] = up ? 1 : 0;     /* x_j - lo_j */
-            S[c * M + 2 * j + 1] = up ? 0 : 1; /* hi_j - x_j */
-        }
-    }
-    {
-        long e = 0;
-        for (int j = 0; j < D; ++j)
-            for (long c = 0; c < V; ++c)
-                if (!((c >> j) & 1)) { Ed[2 * e] = (int32_t)c; Ed[2 * e + 1] = (int32_t)(c | (1L << j)); ++e; }
-    }
+    memcpy(X, X0, sizeof(double) * (size_t)V * D);
+    for (long v = 0; v < V; ++v) memcpy(S + v * M, S0 + v * m, (size_t)m);
+    memcpy(Ed, E0, sizeof(int32_t) * (size_t)E * 2);
 
     double *Hm = NULL;   /* memoised h^(l-1)(v) for the layer being subdivided */
     double *tmp = (double *)malloc(sizeof(double) * (size_t)maxw);
@@ -219,11 +269,15 @@ pcxo_result *pcxo_extract(const pcxo_net *net, const double *lo, const double *h
     int status = PCXO_OK;
     const char *why = "";
     int step = 0;
-    int entry_base = 2 * D;
+    int entry_base = m;
 
     for (int l = 1; l <= nsub && status == PCXO_OK; ++l) {
         const int nin = net->widths[l - 1], nl = net->widths[l];
         const double *W = net->W[l - 1], *b = net->b[l - 1];
+        if (prune) {
+            V = prune_complex(net, l, mutation, X, S, M, Ed, V, &E, &status);
+            if (status != PCXO_OK) { why = "oom"; break; }
+        }
         /* memoise h^(l-1) at every current vertex by the forward pass from coordinates */
         free(Hm);
         long capH = capV;
@@ -334,7 +388,7 @@ pcxo_result *pcxo_extract(const pcxo_net *net, const double *lo, const double *h
                 if (zeros != D - 1) { status = PCXO_ERR_DEGENERATE; why = "edge without D-1 zeros"; break; }
                 for (int k = 0; k < n; ++k) {
                     if (se[k] != 0) continue;
-                    int box = k < 2 * D;
+                    int box = k < m;  /* domain entries are perturbed only to + */
                     for (int sg = 1; sg >= -1; sg -= 2) {
                         if (box && sg < 0) continue;
                         if (mutation == 1 && sg < 0) continue;
@@ -375,6 +429,76 @@ pcxo_result *pcxo_extract(const pcxo_net *net, const double *lo, const double *h
     r->V = V; r->E = E; r->X = X; r->S = S; r->edges = Ed;
     if (status != PCXO_OK) fail(r, status, why);
     r->n_steps = step < nsteps ? step : nsteps;
+    return r;
+}
+
+/* The box [lo, hi]^D: entry 2j is x_j - lo_j >= 0, entry 2j+1 is hi_j - x_j >= 0.
+ * Corner c has x_j = hi_j if bit j of c is set, else lo_j; corners at Hamming
+ * distance one share an edge. */
+pcxo_result *pcxo_extract(const pcxo_net *net, const double *lo, const double *hi,
+                          int include_output, int prune, int mutation) {
+    const int D = net->D;
+    if (D < 1 || D > 20) {
+        pcxo_result *r = (pcxo_result *)calloc(1, sizeof(pcxo_result));
+        if (r) fail(r, PCXO_ERR_INVALID, "bad widths");
+        return r;
+    }
+    for (int j = 0; j < D; ++j)
+        if (!(lo[j] < hi[j])) {
+            pcxo_result *r = (pcxo_result *)calloc(1, sizeof(pcxo_result));
+            if (r) fail(r, PCXO_ERR_INVALID, "empty box");
+            return r;
+        }
+    const long nv = 1L << D, ne = (long)D << (D - 1);
+    const int m = 2 * D;
+    double *X0 = (double *)malloc(sizeof(double) * (size_t)nv * D);
+    int8_t *S0 = (int8_t *)malloc((size_t)nv * m);
+    int32_t *E0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ne * 2);
+    pcxo_result *r = NULL;
+    if (X0 && S0 && E0) {
+        for (long c = 0; c < nv; ++c)
+            for (int j = 0; j < D; ++j) {
+                int up = (int)((c >> j) & 1);
+                X0[c * D + j] = up ? hi[j] : lo[j];
+                S0[c * m + 2 * j] = up ? 1 : 0;     /* x_j - lo_j */
+                S0[c * m + 2 * j + 1] = up ? 0 : 1; /* hi_j - x_j */
+            }
+        long e = 0;
+        for (int j = 0; j < D; ++j)
+            for (long c = 0; c < nv; ++c)
+                if (!((c >> j) & 1)) { E0[2 * e] = (int32_t)c; E0[2 * e + 1] = (int32_t)(c | (1L << j)); ++e; }
+        r = extract_core(net, m, nv, X0, S0, ne, E0, include_output, prune, mutation);
+    }
+    free(X0); free(S0); free(E0);
+    return r;
+}
+
+/* The simplex with corners P_0..P_D (rows of `corners`, affinely independent):
+ * entry i is the barycentric coordinate of x for P_i, >= 0 inside (the facet
+ * opposite P_i is its zero set). Corner i is + at entry i and 0 at the D
+ * others; every pair of corners shares an edge, in order (0,1), (0,2), ...,
+ * (D-1,D). */
+pcxo_result *pcxo_extract_simplex(const pcxo_net *net, const double *corners, int include_output, int prune,
+                                  int mutation) {
+    const int D = net->D;
+    if (D < 1 || D > 20) {
+        pcxo_result *r = (pcxo_result *)calloc(1, sizeof(pcxo_result));
+        if (r) fail(r, PCXO_ERR_INVALID, "bad widths");
+        return r;
+    }
+    const long nv = D + 1, ne = (long)D * (D + 1) / 2;
+    const int m = D + 1;
+    int8_t *S0 = (int8_t *)calloc((size_t)nv * m, 1);
+    int32_t *E0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ne * 2);
+    pcxo_result *r = NULL;
+    if (S0 && E0) {
+        for (long i = 0; i < nv; ++i) S0[i * m + i] = 1;
+        long e = 0;
+        for (int i = 0; i < nv; ++i)
+            for (int j = i + 1; j < nv; ++j) { E0[2 * e] = i; E0[2 * e + 1] = j; ++e; }
+        r = extract_core(net, m, nv, corners, S0, ne, E0, include_output, prune, mutation);
+    }
+    free(S0); free(E0);
     return r;
 }
 
