@@ -122,7 +122,9 @@ def pmc_summary(fetch_csv, write_csv):
         scale = 2.0 ** 30 / (probe[0] * 1024.0)   # bytes per counter KiB
         per = {}
         for r in rows:
-            fam = next((f for k, f in KERNEL_FAMILY.items() if r["Kernel_Name"].startswith(k)), None)
+            name = r["Kernel_Name"]
+            name = name[5:] if name.startswith("void ") else name  # templates carry their return type
+            fam = next((f for k, f in KERNEL_FAMILY.items() if name.startswith(k)), None)
             if fam is None:
                 continue
             per.setdefault(fam, []).append(float(r["Counter_Value"]) * 1024.0 * scale)
@@ -346,6 +348,46 @@ def form_levelset(args, pcx, wl, torch):
             "results": out}
 
 
+def form_simplex(args, pcx, wl, torch):
+    """Hypercube vs simplex domain of the same volume (Sec. 5.2: the simplex has
+    D + 1 corners instead of 2^D): an MLP 6-32-32-1, seeds 6."""
+    import math
+    D = 6
+    net = wl.he_mlp([D, 32, 32, 1], 6)
+    m = pcx.MLP.from_net(net)
+    box = wl.cube(D)
+    s = 2.0 * math.factorial(D) ** (1.0 / D)
+    corners = np.vstack([-np.ones(D)] + [-np.ones(D) + s * np.eye(D)[i] for i in range(D)])
+    res = {}
+    for name, run in (("hypercube", lambda: pcx.extract(m, box.lo, box.hi)),
+                      ("simplex", lambda: pcx.extract_simplex(m, corners))):
+        for _ in range(max(1, args.warmup)):
+            run().close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cx = run()
+            inf = cx.info()
+            cx.close()
+        torch.cuda.synchronize()
+        T = (time.perf_counter() - t0) / args.steps
+        cx = run()
+        S = cx.signs()
+        cx.close()
+        mdom = 2 * D if name == "hypercube" else D + 1
+        boundary = int(np.any(S[:, :mdom] == 0, axis=1).sum())
+        res[name] = {"ms": T * 1e3, "V": inf.V, "E": inf.E, "splits": inf.total_splits,
+                     "boundary_vertices": boundary, "interior_vertices": inf.V - boundary}
+        print(f"[bench] simplex form {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
+    m.close()
+    sp = res["simplex"]
+    return {"metric": METRIC, "value": sp["splits"] / (sp["ms"] / 1e3), "unit": "edges subdivided/s (simplex domain)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sp["ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "MLP 6-32-32-1 (seed 6) on [-1,1]^6 vs the corner simplex of equal volume",
+                       "parallelism": "single GPU"}, "results": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +396,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain_large", help="workloads function name (default: the 768-neuron net)")
     ap.add_argument("--pairing", default="hash", choices=["hash", "sort"], help="step-5 grouping of 2-face keys")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "backward", "levelset"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "backward", "levelset", "simplex"],
                     help="plain (default): one large network; the others measure the systems forms")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 1 GiB device copy (reads 1 GiB, writes 1 GiB): the reference for "
@@ -386,7 +428,7 @@ def main():
         del a, b
     if args.form != "plain":
         fn = {"batched": form_batched, "served": form_served, "backward": form_backward,
-              "levelset": form_levelset}[args.form]
+              "levelset": form_levelset, "simplex": form_simplex}[args.form]
         print(json.dumps(fn(args, pcx, wl, torch)), flush=True)
         return
 

@@ -105,6 +105,34 @@ void pcx_mlp_free(pcx_mlp *mlp);
 int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts,
                 pcx_complex **out);
 
+/* The same on the simplex with corners P_0..P_D: `corners` holds (D+1) x D host
+ * doubles, row i = P_i, affinely independent (else PCX_ERR_INVALID). The
+ * domain is given by m = D + 1 half-spaces (Sec. 4.1; the simplex domain is the
+ * paper's remedy for the 2^D corners of the hypercube, Sec. 5.2): sign entry i
+ * is the barycentric coordinate of P_i, + inside, 0 on the facet opposite P_i.
+ * These D + 1 entries take word 0 (entry i at bits 2i); the layers follow as
+ * for the box. Initial skeleton: corner i is vertex i, edges (i, j) for i < j in
+ * lexicographic order. Vertices on a facet lie on it up to rounding (their
+ * zero entries are exact in the sign-vector). Every option of pcx_extract
+ * applies (pruning, tape, pairing). */
+int pcx_extract_simplex(const pcx_mlp *mlp, const double *corners, const pcx_opts *opts, pcx_complex **out);
+
+/* Higher cells by repeated perturbation (Sec. 4.1): the parents of a k-cell come
+ * from perturbing each zero of its sign-vector to + and - (domain zeros only to
+ * +), starting from the edges (sign-vector of an edge = join of its vertices',
+ * Sec. 3.5). counts (host, D + 1 entries) receives the f-vector: counts[k] =
+ * number of k-cells, counts[0] = V, counts[1] = E, counts[D] = regions. For a
+ * complex on a ball-shaped domain the alternating sum is 1 (Euler). Distinct
+ * cells are told apart by a 128-bit hash of their sign-vector; two cells with
+ * equal first 64 bits but different second halves give PCX_ERR_DEVICE. Runs on
+ * `stream` and returns when done; temporary device memory is released. */
+int pcx_cell_counts(const pcx_complex *cx, int64_t *counts, void *stream);
+
+/* Sign-vectors of all regions (D-cells), packed like the vertex rows (Wd words
+ * each, host memory), sorted lexicographically by word. *n receives the count;
+ * with rows == NULL only the count is computed. */
+int pcx_regions(const pcx_complex *cx, uint64_t *rows, int64_t *n, void *stream);
+
 int pcx_complex_info(const pcx_complex *cx, pcx_info *info);
 
 /* Per-step counters, n_steps rows of 4 int64 (host buffer): vertices and

@@ -9,6 +9,7 @@ from .oracle import (  # noqa: F401
     OracleResult,
     build,
     extract,
+    extract_simplex,
     forward,
     vertex_solve,
 )

@@ -55,6 +55,8 @@ def _load():
     lib.pcxo_extract.restype = vp
     lib.pcxo_extract.argtypes = [C.POINTER(_Net), C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.c_int,
                                  C.c_int]
+    lib.pcxo_extract_simplex.restype = vp
+    lib.pcxo_extract_simplex.argtypes = [C.POINTER(_Net), C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int]
     lib.pcxo_free.argtypes = [vp]
     for name, rt in [("pcxo_status", C.c_int), ("pcxo_V", C.c_long), ("pcxo_E", C.c_long),
                      ("pcxo_M", C.c_int), ("pcxo_n_steps", C.c_int), ("pcxo_min_margin", C.c_double)]:
@@ -138,6 +140,37 @@ def extract(net, lo, hi, include_output: bool = False, mutation: int = 0, prune:
         return OracleResult(D, M, X, S, Ed, steps, float(lib.pcxo_min_margin(r)))
     finally:
         lib.pcxo_free(r)
+
+
+def _result(lib, r, D) -> OracleResult:
+    if not r:
+        raise MemoryError("oracle allocation failed")
+    try:
+        st = lib.pcxo_status(r)
+        if st != OK:
+            raise OracleError(st, lib.pcxo_message(r).decode())
+        V, E, M, ns = lib.pcxo_V(r), lib.pcxo_E(r), lib.pcxo_M(r), lib.pcxo_n_steps(r)
+        X = np.empty((V, D), np.float64)
+        S = np.empty((V, M), np.int8)
+        Ed = np.empty((E, 2), np.int32)
+        steps = np.empty((ns, 4), np.int64)
+        lib.pcxo_copy(r, X.ctypes.data, S.ctypes.data, Ed.ctypes.data, steps.ctypes.data)
+        return OracleResult(D, M, X, S, Ed, steps, float(lib.pcxo_min_margin(r)))
+    finally:
+        lib.pcxo_free(r)
+
+
+def extract_simplex(net, corners, include_output: bool = False, mutation: int = 0,
+                    prune: bool = False) -> OracleResult:
+    """Edge subdivision on the simplex with the given D + 1 corners (rows); the
+    first D + 1 sign-vector entries are the barycentric coordinates."""
+    lib = _load()
+    h = _NetHolder(net.widths, net.W, net.b)
+    D = int(h.widths[0])
+    P = np.ascontiguousarray(corners, dtype=np.float64)
+    assert P.shape == (D + 1, D)
+    r = lib.pcxo_extract_simplex(C.byref(h.c), _dp(P), int(bool(include_output)), int(bool(prune)), int(mutation))
+    return _result(lib, r, D)
 
 
 def forward(net, x) -> np.ndarray:

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -362,19 +363,29 @@ void pcx_mlp_free(pcx_mlp *m) {
     delete m;
 }
 
-int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out) {
-    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
-    *out = nullptr;
-    if (!mlp || !lo || !hi) return fail(PCX_ERR_INVALID, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// The domain of Sec. 4.1: m half-spaces (the first m sign entries, all in word
+// 0) and its 1-skeleton. The box is generated on the device from lo / hi; any
+// other domain brings its vertices (coordinates and word 0) and edges.
+struct Domain {
+    int m = 0;
+    const double *lo = nullptr, *hi = nullptr;  // the box
+    std::vector<double> X0;                     // [nv][D]
+    std::vector<uint64_t> W0;                   // [nv] word 0 of each vertex
+    std::vector<int2> E0;                       // [ne]
+};
+
+int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pcx_complex **out) {
     pcx_opts o{};
     if (opts) o = *opts;
     const int D = mlp->D, L = mlp->L;
-    for (int j = 0; j < D; ++j)
-        if (!(lo[j] < hi[j])) return fail(PCX_ERR_INVALID, "box must have lo < hi in every coordinate");
     const int nsub = o.include_output ? L : L - 1;
     std::vector<int> lw(nsub + 1);
     lw[0] = 1;
-    int M = 2 * D, ZS = 1, n_steps = 0;
+    int M = dom.m, ZS = 1, n_steps = 0;
     for (int l = 0; l < nsub; ++l) {
         const int N = mlp->widths[l + 1];
         if (N > kMaxWidth) return fail(PCX_ERR_INVALID, "subdivided layers wider than 256 are not supported");
@@ -407,11 +418,12 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
 
     // host-side tables
     std::vector<uint64_t> valid(Wd, 0);
-    for (int e = 0; e < 2 * D; ++e) valid[0] |= 1ull << (2 * e);
+    for (int e = 0; e < dom.m; ++e) valid[0] |= 1ull << (2 * e);
     for (int l = 0; l < nsub; ++l)
         for (int c = 0; c < mlp->widths[l + 1]; ++c) valid[lw[l] + (c >> 5)] |= 1ull << (2 * (c & 31));
 
-    const size_t V0 = (size_t)1 << D, E0 = (size_t)D << (D - 1);
+    const bool box = dom.lo != nullptr;
+    const size_t V0 = box ? (size_t)1 << D : dom.W0.size(), E0 = box ? (size_t)D << (D - 1) : dom.E0.size();
     HIPCHK(hipHostMalloc((void **)&x.hctr, CTR_COUNT * sizeof(int), hipHostMallocDefault));
     {
         void *p;
@@ -423,13 +435,13 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
         if ((rc = x.arena.alloc(&p, (size_t)kSelBlocks * sizeof(int)))) return rc;
         x.b.SELCNT = (int *)p;
     }
-    double *dbox;
-    {
+    double *dbox = nullptr;
+    if (box) {
         void *p;
         if ((rc = x.arena.alloc(&p, 2 * D * sizeof(double)))) return rc;
         dbox = (double *)p;
-        HIPCHK(hipMemcpyAsync(dbox, lo, D * sizeof(double), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(dbox + D, hi, D * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dbox, dom.lo, D * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(dbox + D, dom.hi, D * sizeof(double), hipMemcpyHostToDevice, st));
     }
     if ((rc = x.ensure_vertices(std::max<size_t>({V0, 1024, (size_t)mlp->hintV.load()}), 0))) return rc;
     if ((rc = x.ensure_edges(std::max<size_t>({E0, 4096, (size_t)mlp->hintE.load()}), 0, 0))) return rc;
@@ -451,7 +463,17 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
         }
     } evg{t0, t1};
     HIPCHK(hipEventRecord(t0, st));
-    launch_init_box(x.b, D, Wd, dbox, dbox + D, st);
+    std::vector<uint64_t> rows0;
+    if (box) {
+        launch_init_box(x.b, D, Wd, dbox, dbox + D, st);
+    } else {
+        rows0.assign(V0 * (size_t)Wd, 0ull);
+        for (size_t v = 0; v < V0; ++v) rows0[v * Wd] = dom.W0[v];
+        HIPCHK(hipMemcpyAsync(x.b.X, dom.X0.data(), V0 * D * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(x.b.SG, rows0.data(), rows0.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(x.b.EDG, dom.E0.data(), E0 * sizeof(int2), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // the host vectors are not kept
+    }
     HIPCHK(hipGetLastError());
 
     std::vector<int64_t> steps((size_t)n_steps * 4, 0);
@@ -590,6 +612,7 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
 
     pcx_complex *cx = new pcx_complex();
+    cx->valid = valid;
     cx->D = D;
     cx->M = M;
     cx->Wd = Wd;
@@ -633,6 +656,66 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     m->hintE.store(std::max<int64_t>(m->hintE.load(), E));
     *out = cx;
     return PCX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out) {
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!mlp || !lo || !hi) return fail(PCX_ERR_INVALID, "NULL argument");
+    for (int j = 0; j < mlp->D; ++j)
+        if (!(lo[j] < hi[j])) return fail(PCX_ERR_INVALID, "box must have lo < hi in every coordinate");
+    Domain dom;
+    dom.m = 2 * mlp->D;
+    dom.lo = lo;
+    dom.hi = hi;
+    return extract_impl(mlp, dom, opts, out);
+}
+
+int pcx_extract_simplex(const pcx_mlp *mlp, const double *corners, const pcx_opts *opts, pcx_complex **out) {
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!mlp || !corners) return fail(PCX_ERR_INVALID, "NULL argument");
+    const int D = mlp->D;
+    // affinely independent corners: the (D+1) x (D+1) matrix of rows (P_i, 1) is regular
+    std::vector<double> T((size_t)(D + 1) * (D + 1));
+    double scale = 0.0;
+    for (int i = 0; i <= D; ++i) {
+        for (int k = 0; k < D; ++k) {
+            const double v = corners[(size_t)i * D + k];
+            if (!std::isfinite(v)) return fail(PCX_ERR_INVALID, "simplex corners must be finite");
+            T[(size_t)i * (D + 1) + k] = v;
+            scale = std::max(scale, std::fabs(v));
+        }
+        T[(size_t)i * (D + 1) + D] = 1.0;
+    }
+    double det = 1.0;
+    for (int c = 0; c <= D; ++c) {
+        int piv = c;
+        for (int r = c + 1; r <= D; ++r)
+            if (std::fabs(T[(size_t)r * (D + 1) + c]) > std::fabs(T[(size_t)piv * (D + 1) + c])) piv = r;
+        const double p = T[(size_t)piv * (D + 1) + c];
+        if (std::fabs(p) <= 1e-12 * std::max(1.0, scale)) return fail(PCX_ERR_INVALID, "simplex corners are affinely dependent");
+        if (piv != c)
+            for (int k = 0; k <= D; ++k) std::swap(T[(size_t)c * (D + 1) + k], T[(size_t)piv * (D + 1) + k]);
+        det *= p;
+        for (int r = c + 1; r <= D; ++r) {
+            const double f = T[(size_t)r * (D + 1) + c] / p;
+            for (int k = c; k <= D; ++k) T[(size_t)r * (D + 1) + k] -= f * T[(size_t)c * (D + 1) + k];
+        }
+    }
+    (void)det;
+    Domain dom;
+    dom.m = D + 1;
+    dom.X0.assign(corners, corners + (size_t)(D + 1) * D);
+    dom.W0.resize(D + 1);
+    for (int i = 0; i <= D; ++i) dom.W0[i] = 1ull << (2 * i);  // + at its own barycentric entry, 0 at the others
+    for (int i = 0; i <= D; ++i)
+        for (int j = i + 1; j <= D; ++j) dom.E0.push_back(make_int2(i, j));
+    return extract_impl(mlp, dom, opts, out);
 }
 
 int pcx_complex_info(const pcx_complex *cx, pcx_info *info) {

@@ -25,7 +25,8 @@ PAIRING = {"hash": 0, "sort": 1}
 
 # every symbol include/pcx.h declares
 SYMBOLS = [
-    "pcx_last_error", "pcx_mlp_create", "pcx_mlp_free", "pcx_extract", "pcx_complex_info",
+    "pcx_last_error", "pcx_mlp_create", "pcx_mlp_free", "pcx_extract", "pcx_extract_simplex", "pcx_cell_counts",
+    "pcx_regions", "pcx_complex_info",
     "pcx_complex_steps", "pcx_complex_copy", "pcx_complex_device", "pcx_complex_kernel_time",
     "pcx_complex_free", "pcx_cache_trim", "pcx_complex_copy_device", "pcx_backward",
     "pcx_extract_batch", "pcx_batch_info", "pcx_batch_copy", "pcx_batch_summary", "pcx_batch_free",
@@ -88,6 +89,9 @@ def _load():
     lib.pcx_mlp_free.argtypes = [vp]
     lib.pcx_mlp_free.restype = None
     lib.pcx_extract.argtypes = [vp, PD, PD, C.POINTER(_Opts), C.POINTER(vp)]
+    lib.pcx_extract_simplex.argtypes = [vp, PD, C.POINTER(_Opts), C.POINTER(vp)]
+    lib.pcx_cell_counts.argtypes = [vp, C.POINTER(i64), vp]
+    lib.pcx_regions.argtypes = [vp, vp, C.POINTER(i64), vp]
     lib.pcx_complex_info.argtypes = [vp, C.POINTER(_Info)]
     lib.pcx_complex_steps.argtypes = [vp, vp]
     lib.pcx_complex_copy.argtypes = [vp, vp, vp, vp]
@@ -192,14 +196,16 @@ class Info:
     time_ms: float
 
 
-def sign_layout(widths: Sequence[int], include_output: bool = False):
-    """(word, shift) of every sign-vector entry under the packing of pcx.h:
-    box entries in word 0, each subdivided layer from a fresh word."""
+def sign_layout(widths: Sequence[int], include_output: bool = False, m: Optional[int] = None):
+    """(word, shift) of every sign-vector entry under the packing of pcx.h: the
+    m domain entries in word 0 (2D for the box, D+1 for a simplex), each
+    subdivided layer from a fresh word."""
     D = int(widths[0])
+    m = 2 * D if m is None else int(m)
     L = len(widths) - 1
     nsub = L if include_output else L - 1
-    word = [0] * (2 * D)
-    shift = [2 * e for e in range(2 * D)]
+    word = [0] * m
+    shift = [2 * e for e in range(m)]
     lw = 1
     for l in range(1, nsub + 1):
         for i in range(int(widths[l])):
@@ -212,10 +218,11 @@ def sign_layout(widths: Sequence[int], include_output: bool = False):
 class Complex:
     """An extracted 1-skeleton held on the device (``pcx_complex``)."""
 
-    def __init__(self, handle, widths, include_output):
+    def __init__(self, handle, widths, include_output, m=None):
         self._h = handle
         self.widths = list(widths)
         self.include_output = include_output
+        self.m = 2 * int(widths[0]) if m is None else int(m)  # domain entries
 
     def info(self) -> Info:
         i = _Info()
@@ -241,11 +248,27 @@ class Complex:
         """Sign-vectors as int8 [V, M] in {+1, 0, -1}."""
         if packed is None:
             _, packed, _ = self.copy()
-        word, shift, _ = sign_layout(self.widths, self.include_output)
+        word, shift, _ = sign_layout(self.widths, self.include_output, self.m)
         codes = (packed[:, word] >> shift.astype(np.uint64)) & np.uint64(3)
         out = np.zeros(codes.shape, np.int8)
         out[codes == 1] = 1
         out[codes == 2] = -1
+        return out
+
+    def cell_counts(self, stream=None) -> np.ndarray:
+        """``pcx_cell_counts``: the f-vector (f_0 = V, f_1 = E, ..., f_D = regions)."""
+        D = self.info().D
+        out = np.zeros(D + 1, np.int64)
+        _check(_lib.pcx_cell_counts(self._h, out.ctypes.data_as(C.POINTER(C.c_int64)), stream))
+        return out
+
+    def regions(self, stream=None) -> np.ndarray:
+        """``pcx_regions``: packed sign rows of every region, sorted ([n, Wd] uint64)."""
+        n = C.c_int64()
+        _check(_lib.pcx_regions(self._h, None, C.byref(n), stream))
+        out = np.zeros((n.value, self.info().Wd), np.uint64)
+        if n.value:
+            _check(_lib.pcx_regions(self._h, out.ctypes.data, C.byref(n), stream))
         return out
 
     def copy_device(self, coords_ptr=None, signs_ptr=None, edges_ptr=None, stream=None):
@@ -306,6 +329,22 @@ def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=Non
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))
     return Complex(h, mlp.widths, include_output)
+
+
+def extract_simplex(mlp: MLP, corners, include_output: bool = False, timing=0, stream=None, max_bytes: int = 0,
+                    pairing: str = "hash", record_tape: bool = False, prune: bool = False) -> Complex:
+    """``pcx_extract_simplex``: edge subdivision of the simplex with the given D + 1
+    corners (rows); sign entries 0..D are the barycentric coordinates."""
+    P = np.ascontiguousarray(corners, np.float64)
+    if P.shape != (mlp.D + 1, mlp.D):
+        raise ValueError("corners must be (D + 1) x D")
+    tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
+    o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream, 0,
+              int(bool(prune)))
+    h = C.c_void_p()
+    PD = C.POINTER(C.c_double)
+    _check(_lib.pcx_extract_simplex(mlp._h, P.ctypes.data_as(PD), C.byref(o), C.byref(h)))
+    return Complex(h, mlp.widths, include_output, m=mlp.D + 1)
 
 
 @dataclass

@@ -226,15 +226,17 @@ def planar_face_count(X, edges):
     return faces
 
 
-def regions_by_perturbation(S, edges, D):
+def regions_by_perturbation(S, edges, D, m=None):
     """Sign-vectors of all regions, by perturbing every zero of every edge
-    (Sec. 4.1: each zero to + and -, box zeros only to +)."""
+    (Sec. 4.1: each zero to + and -, domain zeros (the first m entries, 2D for
+    the box) only to +)."""
+    m = 2 * D if m is None else m
     regs = set()
     for a, b in edges:
         jn, conf = join(S[a], S[b])
         assert not conf.any()
         zs = np.nonzero(jn == 0)[0]
-        choices = [([1] if e < 2 * D else [1, -1]) for e in zs]
+        choices = [([1] if e < m else [1, -1]) for e in zs]
         for combo in itertools.product(*choices):
             r = jn.copy()
             r[zs] = combo
@@ -293,3 +295,95 @@ def arrangement_counts_3d(W, b, lo, hi):
     V = 8 + n_edge + n_face + n_inner
     E = (3 * 8 + 4 * n_edge + 5 * n_face + 6 * n_inner) // 2
     return V, E
+
+
+# ------------------------------------------------ a domain of half-spaces
+
+def simplex_halfspaces(corners):
+    """(A, c) with A x + c the barycentric coordinates of x for the corners P_0..P_D
+    (rows of ``corners``): entry i is 1 at P_i and 0 on the facet opposite it."""
+    P = np.asarray(corners, np.float64)
+    D = P.shape[1]
+    T = np.hstack([P, np.ones((D + 1, 1))])      # [D+1, D+1]: row i = (P_i, 1)
+    Ti = np.linalg.inv(T)                        # lambda(x) = (x, 1) @ Ti
+    return Ti[:D].T.copy(), Ti[D].copy()
+
+
+def domain_entry_values(net, A, c, x, include_output=False):
+    """Domain entries A x + c, then every subdivided neuron."""
+    x = np.atleast_2d(x)
+    z = forward_all(net, x)
+    n = entry_count(net.widths, include_output) - 2 * x.shape[1]
+    return np.concatenate([x @ A.T + c, z[:, :n]], axis=1)
+
+
+def vertices_halfspaces(net, A, c, include_output=False):
+    """All vertices of the complex on the domain {A x + c >= 0}: every D-subset of
+    entries (domain facets and neurons) under every activation pattern below the
+    deepest one, solved and confirmed by the forward pass (D zeros exactly)."""
+    widths = list(net.widths)
+    D = widths[0]
+    m = len(c)
+    L = len(widths) - 1
+    nsub = L if include_output else L - 1
+    lay = np.array([0] * m + sum(([l] * widths[l] for l in range(1, nsub + 1)), []))
+    M = len(lay)
+    found = {}
+    for Zs in itertools.combinations(range(M), D):
+        deep = int(max(lay[list(Zs)]))
+        free_layers = list(range(1, deep))
+        n_free = sum(widths[l] for l in free_layers)
+        for bits in range(1 << n_free):
+            pattern = {}
+            off = 0
+            for l in free_layers:
+                pattern[l] = np.array([(bits >> (off + i)) & 1 for i in range(widths[l])], bool)
+                off += widths[l]
+            maps = _affine_maps(net, pattern, max(deep, 1), D) if deep >= 1 else []
+            Am = np.zeros((D, D))
+            r = np.zeros(D)
+            for k, e in enumerate(Zs):
+                if e < m:
+                    Am[k] = A[e]
+                    r[k] = -c[e]
+                else:
+                    l = lay[e]
+                    i = e - (m + sum(widths[1:l]))
+                    Gz, cz = maps[l - 1]
+                    Am[k] = Gz[i]
+                    r[k] = -cz[i]
+            if abs(np.linalg.det(Am)) < 1e-12:
+                continue
+            x = np.linalg.solve(Am, r)
+            vals = domain_entry_values(net, A, c, x, include_output)[0]
+            if np.any(vals[:m] < -1e-9):
+                continue
+            zmask = np.abs(vals) < ZERO_TOL
+            if zmask.sum() != D or not all(zmask[e] for e in Zs):
+                continue
+            s = sign_vector(vals)
+            found.setdefault(s.tobytes(), (x, s))
+    X = np.array([v[0] for v in found.values()]).reshape(-1, D)
+    S = np.array([v[1] for v in found.values()], dtype=np.int8).reshape(-1, M)
+    return X, S
+
+
+def edges_by_midpoint_halfspaces(net, A, c, X, S, include_output=False):
+    """Edges among the given vertices of a half-space domain (index pairs i<j):
+    D-1 shared zeros, no +/- conflict, midpoint carrying the join."""
+    D = X.shape[1]
+    out = []
+    Z = S == 0
+    for i in range(len(S)):
+        shared = (Z[i] & Z).sum(1)
+        for j in np.nonzero(shared == D - 1)[0]:
+            if j <= i:
+                continue
+            jn, conf = join(S[i], S[j])
+            if conf.any():
+                continue
+            vals = domain_entry_values(net, A, c, 0.5 * (X[i] + X[j]), include_output)[0]
+            on = jn == 0
+            if np.all(np.abs(vals[on]) < 1e-7) and np.all((np.sign(vals[~on]) == jn[~on]) & (np.abs(vals[~on]) > 1e-12)):
+                out.append((i, j))
+    return np.array(out, dtype=np.int64).reshape(-1, 2)

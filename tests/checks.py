@@ -11,17 +11,19 @@ import numpy as np
 from brute import entry_values, join
 
 
-def unpack_signs(packed: np.ndarray, widths, include_output=False) -> np.ndarray:
+def unpack_signs(packed: np.ndarray, widths, include_output=False, m=None) -> np.ndarray:
     """Packed rows ([V, Wd] uint64) to int8 sign-vectors [V, M] in {+1, 0, -1}.
 
-    Packing of include/pcx.h: 2 bits per entry, 00 = 0, 01 = +, 10 = -; box
-    entry e in word 0 at bits 2e; neuron i of the l-th subdivided layer in word
-    lw_l + i // 32 at bits 2 (i % 32), with lw_1 = 1, lw_{l+1} = lw_l + ceil(N_l / 32)."""
+    Packing of include/pcx.h: 2 bits per entry, 00 = 0, 01 = +, 10 = -; domain
+    entry e (m of them: 2D for the box, D + 1 for a simplex) in word 0 at bits
+    2e; neuron i of the l-th subdivided layer in word lw_l + i // 32 at bits
+    2 (i % 32), with lw_1 = 1, lw_{l+1} = lw_l + ceil(N_l / 32)."""
     packed = np.ascontiguousarray(packed, dtype=np.uint64)
     D = int(widths[0])
+    m = 2 * D if m is None else m
     L = len(widths) - 1
     nsub = L if include_output else L - 1
-    cols = [(0, 2 * e) for e in range(2 * D)]
+    cols = [(0, 2 * e) for e in range(m)]
     lw = 1
     for l in range(1, nsub + 1):
         n = int(widths[l])

@@ -315,3 +315,134 @@ def test_pruning_needs_the_output(oracle_lib):
     box = wl.cube(2)
     with pytest.raises(oracle_lib.OracleError):
         oracle_lib.extract(net, box.lo, box.hi, include_output=False, prune=True)
+
+
+# ------------------------------------------------- simplex domain (Sec. 5.2 outlook, Sec. 4.1)
+
+SIMPLEX_2D = np.array([[-1.0, -1.0], [1.5, -0.8], [-0.7, 1.3]])
+SIMPLEX_3D = np.array([[-1.0, -1, -1], [1.2, -0.9, -1.1], [-0.8, 1.4, -0.7], [-0.9, -0.6, 1.5]])
+
+
+@pytest.mark.parametrize("widths,seed,P,incl", [
+    ([2, 5, 4, 1], 3, SIMPLEX_2D, False), ([2, 6, 1], 4, SIMPLEX_2D, False), ([2, 4, 3, 1], 8, SIMPLEX_2D, True),
+    ([3, 4, 3, 1], 7, SIMPLEX_3D, False), ([3, 5, 1], 9, SIMPLEX_3D, True)])
+def test_simplex_matches_brute_force(oracle_lib, widths, seed, P, incl):
+    """On a simplex (barycentric domain entries) the oracle's vertices and edges
+    are the brute-force ones: every D-subset of facets and neurons solved and
+    confirmed, edges by the midpoint test."""
+    net = wl.he_mlp(widths, seed)
+    r = oracle_lib.extract_simplex(net, P, include_output=incl)
+    A, c = brute.simplex_halfspaces(P)
+    Xb, Sb = brute.vertices_halfspaces(net, A, c, include_output=incl)
+    assert r.V == len(Xb)
+    Eb = brute.edges_by_midpoint_halfspaces(net, A, c, Xb, Sb, include_output=incl)
+    assert_same_complex((r.X, r.S, r.edges), (Xb, Sb, Eb), coord_tol=1e-9)
+    D = widths[0]
+    zdom = (r.S[:, :D + 1] == 0).sum(1)
+    deg = np.bincount(r.edges.ravel(), minlength=r.V)
+    assert np.array_equal(deg, 2 * D - zdom), "degree != 2D - (domain zeros)"
+
+
+def test_simplex_planar_euler_and_regions(oracle_lib):
+    """D = 2: V - E + F = 1 inside the triangle, and F - 1 equals the number of
+    regions found by perturbing edges (domain zeros only to +)."""
+    net = wl.he_mlp([2, 7, 6, 1], 12)
+    r = oracle_lib.extract_simplex(net, SIMPLEX_2D)
+    F = brute.planar_face_count(r.X, r.edges)
+    assert r.V - r.E + F == 2  # the outer face included
+    regs = brute.regions_by_perturbation(r.S, r.edges, 2, m=3)
+    assert len(regs) == F - 1
+
+
+def test_simplex_of_a_single_layer_counts(oracle_lib):
+    """One hidden layer in a triangle: corners, one vertex per (line, side)
+    crossing, one per pair of lines meeting inside."""
+    net = wl.he_mlp([2, 9, 1], 13)
+    r = oracle_lib.extract_simplex(net, SIMPLEX_2D)
+    W, b = net.W[0], net.b[0]
+    P = SIMPLEX_2D
+    n_side = sum(int(np.sum((W @ P[i] + b) * (W @ P[j] + b) < 0)) for i in range(3) for j in range(i + 1, 3))
+    A, c = brute.simplex_halfspaces(P)
+    n_in = 0
+    for i in range(9):
+        for j in range(i + 1, 9):
+            x = np.linalg.solve(W[[i, j]], -b[[i, j]])
+            n_in += int(np.all(A @ x + c > 0))
+    assert r.V == 3 + n_side + n_in
+    assert r.E == (2 * 3 + 3 * n_side + 4 * n_in) // 2
+
+
+# ------------------------------------------------- higher cells by perturbation (Sec. 4.1)
+
+CELL_CASES = [([2, 8, 8, 1], 1, None), ([3, 8, 8, 1], 5, None), ([3, 10, 10, 10, 1], 32, None),
+              ([4, 6, 6, 1], 34, None), ([1, 6, 6, 1], 33, None), ([2, 5, 4, 1], 3, SIMPLEX_2D),
+              ([3, 4, 3, 1], 7, SIMPLEX_3D)]
+
+
+def _complex(oracle_lib, widths, seed, P, incl=False):
+    net = wl.he_mlp(widths, seed)
+    D = widths[0]
+    if P is None:
+        box = wl.cube(D)
+        return net, oracle_lib.extract(net, box.lo, box.hi, include_output=incl), 2 * D
+    return net, oracle_lib.extract_simplex(net, P, include_output=incl), D + 1
+
+
+@pytest.mark.parametrize("widths,seed,P", CELL_CASES)
+def test_cell_counts_satisfy_euler(oracle_lib, widths, seed, P):
+    """The complex fills a convex domain (a ball), so its f-vector has
+    alternating sum 1 (Euler-Poincare) in every dimension D = 1..4."""
+    from oracle.cells import face_counts
+    net, r, m = _complex(oracle_lib, widths, seed, P)
+    f, regs = face_counts(r.S, r.edges, widths[0], m)
+    assert f[0] == r.V and f[1] == r.E
+    assert sum((-1) ** k * x for k, x in enumerate(f)) == 1
+    assert len(regs) == f[-1] and not np.any(regs == 0)
+
+
+def test_regions_planar_and_sampled(oracle_lib):
+    """D = 2: the regions are the bounded faces of the plane graph; D = 2, 3:
+    every random point of the box lies in a region found (its forward-pass
+    sign-vector is one of them)."""
+    from oracle.cells import face_counts
+    for widths, seed in [([2, 8, 8, 1], 1), ([2, 12, 10, 1], 31), ([3, 8, 8, 1], 5)]:
+        net, r, m = _complex(oracle_lib, widths, seed, None)
+        D = widths[0]
+        f, regs = face_counts(r.S, r.edges, D, m)
+        if D == 2:
+            assert f[2] == brute.planar_face_count(r.X, r.edges) - 1
+        box = wl.cube(D)
+        x = np.random.default_rng(seed).uniform(-1, 1, (4000, D))
+        sv = brute.sign_vector(brute.entry_values(net, box.lo, box.hi, x))
+        keys = {row.tobytes() for row in regs}
+        assert all(row.tobytes() in keys for row in sv)
+
+
+def test_single_layer_region_count_2d(oracle_lib):
+    """Lines in general position cutting a convex region: each line adds one
+    region plus one per crossing with an earlier line inside the region."""
+    from oracle.cells import face_counts
+    net = wl.he_mlp([2, 11, 1], 14)
+    box = wl.cube(2)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    f, _ = face_counts(r.S, r.edges, 2, 4)
+    W, b = net.W[0], net.b[0]
+    corners = np.array([[x, y] for x in (-1, 1) for y in (-1, 1)])
+    cuts = sum(int(np.ptp(np.sign(corners @ W[i] + b[i])) > 0) for i in range(11))
+    inner = 0
+    for i in range(11):
+        for j in range(i + 1, 11):
+            p = np.linalg.solve(W[[i, j]], -b[[i, j]])
+            inner += int(np.all(np.abs(p) < 1))
+    assert f[2] == 1 + cuts + inner
+
+
+@pytest.mark.parametrize("mutation", [1, 2])
+def test_cell_mistakes_are_caught(oracle_lib, mutation):
+    from oracle.cells import face_counts
+    bad = False
+    for widths, seed, P in CELL_CASES[:4]:
+        net, r, m = _complex(oracle_lib, widths, seed, P)
+        f, _ = face_counts(r.S, r.edges, widths[0], m, mutation=mutation)
+        bad |= sum((-1) ** k * x for k, x in enumerate(f)) != 1
+    assert bad
