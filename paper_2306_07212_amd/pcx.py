@@ -465,10 +465,18 @@ class Server:
         _check(_lib.pcx_server_wait(self._h, C.c_uint64(ticket), C.byref(r)))
         return _as_dict(r)
 
+    def error(self, ticket: int) -> str:
+        """The failure message of a finished request ("" if it succeeded)."""
+        r = self.wait(ticket)
+        if r["status"] == PCX_OK:
+            return ""
+        _lib.pcx_server_copy(self._h, C.c_uint64(ticket), None, None, None)
+        return _lib.pcx_last_error().decode()
+
     def copy(self, ticket: int):
         r = self.wait(ticket)
         if r["status"] != PCX_OK:
-            raise PcxError(r["status"], "request failed")
+            raise PcxError(r["status"], self.error(ticket))
         mlp = self._keep[ticket][0]
         D = mlp.D
         Wd = 1
