@@ -230,16 +230,31 @@ def form_served(args, pcx, wl, torch):
         srv = pcx.Server()
         t0 = time.perf_counter()
         tickets = []
+        res = [None] * len(reqs)
+        failed = []
+
+        # a client consumes each result as it completes (in submission order) and releases it, as a
+        # serving loop would: finished complexes are the caller's memory until released
+        def consume():
+            for i in range(len(reqs)):
+                while i >= len(tickets):
+                    time.sleep(1e-4)
+                tk = tickets[i]
+                res[i] = srv.wait(tk)
+                if res[i]["status"] != 0:
+                    failed.append((i, res[i]["status"], srv.error(tk)))
+                srv.release(tk)
+
+        import threading
+        th = threading.Thread(target=consume)
+        th.start()
         for a, r, m in zip(arr, reqs, mlps):
             dt = a - (time.perf_counter() - t0)
             if dt > 0:
                 time.sleep(dt)
             tickets.append(srv.submit(m, r.box.lo, r.box.hi))
-        res = [srv.wait(tk) for tk in tickets]
+        th.join()
         st = srv.stats()
-        failed = [(i, x["status"], srv.error(tk)) for i, (x, tk) in enumerate(zip(res, tickets)) if x["status"] != 0]
-        for tk in tickets:
-            srv.release(tk)
         srv.close()
         if failed:
             print(f"[bench] served: {len(failed)} requests failed, first: {failed[:3]}", file=sys.stderr, flush=True)

@@ -125,7 +125,8 @@ int pcx_extract_simplex(const pcx_mlp *mlp, const double *corners, const pcx_opt
  * complex on a ball-shaped domain the alternating sum is 1 (Euler). Distinct
  * cells are told apart by a 128-bit hash of their sign-vector; two cells with
  * equal first 64 bits but different second halves give PCX_ERR_DEVICE. Runs on
- * `stream` and returns when done; temporary device memory is released. */
+ * `stream` and returns when done; temporary device memory is released. A
+ * complex extracted with pcx_opts.prune is a sub-complex: PCX_ERR_INVALID. */
 int pcx_cell_counts(const pcx_complex *cx, int64_t *counts, void *stream);
 
 /* Sign-vectors of all regions (D-cells), packed like the vertex rows (Wd words

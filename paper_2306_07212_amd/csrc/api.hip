@@ -160,6 +160,7 @@ struct Extraction {
         if ((rc = grow_keep(b.EDG, c0, need, used, 1))) return rc;
         if ((rc = grow_keep(b.NXT, c1, need, used, 1))) return rc;
         Ecap = std::min(c0, c1);
+        if ((rc = grow_scratch(b.SPLX, Ecap, Ecap))) return rc;  // chunk match lists: edge capacity
         // the compaction writes up to E split ids before the host learns S,
         // so the split list always has the edge capacity
         if (Ecap > Scap) {
@@ -613,6 +614,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
 
     pcx_complex *cx = new pcx_complex();
     cx->valid = valid;
+    cx->pruned = x.prune;
     cx->D = D;
     cx->M = M;
     cx->Wd = Wd;

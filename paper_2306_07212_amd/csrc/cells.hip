@@ -200,6 +200,7 @@ int grid_for(int64_t waves) { return (int)std::max<int64_t>(1, std::min<int64_t>
 int cells_run(const pcx_complex *cx, hipStream_t st, std::vector<int64_t> &counts, Arena &ar, int2 **regions,
               unsigned long long **rkeys, int64_t *nreg) {
     const int D = cx->D, Wd = cx->Wd;
+    if (cx->pruned) return fail(PCX_ERR_INVALID, "cells need the whole complex: this one was pruned");
     counts.assign(D + 1, 0);
     counts[0] = cx->V;
     counts[1] = cx->E;
@@ -221,6 +222,7 @@ int cells_run(const pcx_complex *cx, hipStream_t st, std::vector<int64_t> &count
         const int64_t cand = n * 2 * (D - k);
         size_t tsz = 256;
         while ((double)tsz < 2.0 * (double)cand / (double)(k + 2)) tsz <<= 1;
+        if (tsz > ((size_t)1 << 30)) return fail(PCX_ERR_CAPACITY, "too many cells for one table (more than 2^29)");
         CellTable T;
         if ((rc = ar.alloc(&p, tsz * sizeof(unsigned long long)))) return rc;
         T.key = (unsigned long long *)p;

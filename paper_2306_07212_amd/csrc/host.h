@@ -52,6 +52,7 @@ struct pcx_complex {
     int D = 0, M = 0, Wd = 0, n_steps = 0;
     int64_t V = 0, E = 0;
     std::vector<uint64_t> valid;  // [Wd] 01 at every entry in use
+    bool pruned = false;          // extracted with pcx_opts.prune: a sub-complex, not the whole domain
     double *X = nullptr;
     uint64_t *SG = nullptr;
     int2 *EDG = nullptr;

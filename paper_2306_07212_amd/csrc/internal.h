@@ -64,6 +64,7 @@ struct Bufs {
     int2 *EDG;        // [Ecap]
     uint16_t *NXT;    // [Ecap]
     int *SPL;         // [Scap]
+    int *SPLX;        // [Ecap] per-chunk match lists of the compaction (chunk c at its own edge range)
     uint32_t *K32a, *K32b, *VALa, *VALb;  // [Kcap] radix-sort ping-pong
     uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot
     uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus

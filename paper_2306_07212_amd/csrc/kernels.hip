@@ -80,7 +80,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // RT: 16-row tiles per wave; WAVES: waves per workgroup, 4 per 64-row band of
 // column blocks (wave w: columns [64 (w%4), +64), row band w/4).
-template <int MK, int RT, int WAVES, int MINW, bool DB>
+template <int MK, int RT, int WAVES, int MINW, bool DB, int PF>
 __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, const double *in, int in_stride,
                                                                 int relu, int V, int K, int N,
                                                                 const double *__restrict__ Wt,
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
     const int wc = t % kMaxWidth, wk = (t / kMaxWidth) * WPT;
     const bool arow = v0 + ar < V;
     const double *arow_p = in + (size_t)(v0 + ar) * in_stride;
-    double pa[APT], pw[WPT];
-    auto fetch = [&](int k0) {
+    double pa[PF][APT], pw[PF][WPT];  // PF chunks of staged loads in flight
+    auto fetch = [&](int k0, int slot) {
 #pragma unroll
         for (int i = 0; i < APT; ++i) {
             double h = 0.0;
@@ -110,11 +110,11 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
                 h = arow_p[k0 + ak + i];
                 if (relu) h = h > 0.0 ? h : 0.0;
             }
-            pa[i] = h;
+            pa[slot][i] = h;
         }
 #pragma unroll
         for (int i = 0; i < WPT; ++i)
-            pw[i] = (k0 + wk + i < K && wc < N) ? Wt[(size_t)(k0 + wk + i) * N + wc] : 0.0;
+            pw[slot][i] = (k0 + wk + i < K && wc < N) ? Wt[(size_t)(k0 + wk + i) * N + wc] : 0.0;
     };
     dbl4 acc[RT][4];
 #pragma unroll
@@ -124,11 +124,17 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
     const int col0 = (w & 3) * 64;
     const int rb = (w >> 2) * RT * 16;
     const bool wave_live = col0 < N;
-    auto put = [&](int buf) {
+    double bv[4];  // this lane's bias values, loaded before the main loop
 #pragma unroll
-        for (int i = 0; i < APT; ++i) as[buf][ak + i][ar] = pa[i];
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = col0 + ct * 16 + (l & 15);
+        bv[ct] = col < N ? bias[col] : 0.0;
+    }
+    auto put = [&](int buf, int slot) {
 #pragma unroll
-        for (int i = 0; i < WPT; ++i) ws[buf][wk + i][wc] = pw[i];
+        for (int i = 0; i < APT; ++i) as[buf][ak + i][ar] = pa[slot][i];
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) ws[buf][wk + i][wc] = pw[slot][i];
     };
     auto compute = [&](int buf) {
         if (!wave_live) return;
@@ -146,25 +152,28 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
                     acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[rt], bf[ct], acc[rt][ct], 0, 0, 0);
         }
     };
-    fetch(0);
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+        if (p * MK < K) fetch(p * MK, p);
     if (DB) {
         // one barrier per chunk: compute from one buffer while the next chunk is stored into the other
-        put(0);
+        put(0, 0);
         __syncthreads();
         int c = 0;
         for (int k0 = 0; k0 < K; k0 += MK, ++c) {
             const bool more = k0 + MK < K;
-            if (more) fetch(k0 + MK);
+            if (k0 + PF * MK < K) fetch(k0 + PF * MK, c % PF);
             compute(c & 1);
-            if (more) put((c & 1) ^ 1);
+            if (more) put((c & 1) ^ 1, (c + 1) % PF);
             __syncthreads();
         }
     } else {
-        for (int k0 = 0; k0 < K; k0 += MK) {
+        int c = 0;
+        for (int k0 = 0; k0 < K; k0 += MK, ++c) {
             __syncthreads();
-            put(0);
+            put(0, c % PF);
             __syncthreads();
-            if (k0 + MK < K) fetch(k0 + MK);
+            if (k0 + PF * MK < K) fetch(k0 + PF * MK, c % PF);
             compute(0);
         }
     }
@@ -186,7 +195,7 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
                 const bool ok = v < V && col < N;
                 double z = 0.0;
                 if (ok) {
-                    z = acc[rt][ct][i] + bias[col];
+                    z = acc[rt][ct][i] + bv[ct];
                     b.Z[(size_t)v * ZS + col] = z;
                     zero |= (z == 0.0);
                 }
@@ -216,7 +225,7 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
     if (V <= 0) return;
     if (N > 128 && N <= kMaxWidth && K >= 16) {
         const int grid = (V + 63) / 64;
-        hipLaunchKernelGGL((k_gemm_mfma<8, 2, 8, 4, false>), dim3(grid), dim3(512), 0, st, b, ZS, in, in_stride, relu, V, K, N, Wt,
+        hipLaunchKernelGGL((k_gemm_mfma<8, 2, 8, 4, false, 1>), dim3(grid), dim3(512), 0, st, b, ZS, in, in_stride, relu, V, K, N, Wt,
                            bias, Wd, lw0);
         return;
     }
@@ -257,56 +266,26 @@ void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ehint, 
 // ---------------------------------------------- step 3: splitting edges
 //
 // Ordered stream compaction of {e : NXT[e] == target}. The edge array is cut
-// into kSelBlocks contiguous chunks, one per workgroup. The first kernel counts
-// the matches of each chunk; the second re-reads its chunk, takes its offset
-// as the sum of the counts of the chunks before it, and writes the matching
-// ids in order (wave ballot / prefix sum inside each tile). No workgroup ever
-// waits on another, so the scan runs at streaming speed on all XCDs.
+// into kSelBlocks contiguous chunks, one per workgroup. The first kernel reads
+// its chunk once and writes the matching ids in order (wave ballot / prefix sum
+// inside each tile) to the chunk's own range of SPLX, with the chunk's count;
+// the second moves each chunk's matches to its offset in SPL, the sum of the
+// counts before it (work proportional to the matches, not to the edges). No
+// workgroup ever waits on another, so the scan runs at streaming speed on all
+// XCDs and reads each next-crossing once per step.
 __device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
     const int per = ((E + (int)gridDim.x - 1) / (int)gridDim.x + kSelItems - 1) / kSelItems * kSelItems;
     c0 = min(E, (int)blockIdx.x * per);
     c1 = min(E, c0 + per);
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_count(Bufs b, uint16_t target) {
+__global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target) {
     __shared__ int s_w[kThreads / 64];
-    const int E = b.CTR[CTR_E];
-    int c0, c1;
-    sel_chunk(E, c0, c1);
-    int cnt = 0;
-    for (int base = c0 + threadIdx.x * kSelItems; base < c1; base += kSelTile)
-        cnt += __popc(match16(b.NXT, base, c1, target));
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
-        b.SELCNT[blockIdx.x] = t;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_sel_scatter(Bufs b, uint16_t target) {
-    __shared__ int s_w[kThreads / 64];
-    __shared__ int s_base;
     const int E = b.CTR[CTR_E];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int c0, c1;
     sel_chunk(E, c0, c1);
-    // offset of this chunk: sum of the counts of the chunks before it
-    int pre = 0;
-    for (int i = t; i < (int)blockIdx.x; i += kThreads) pre += b.SELCNT[i];
-    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
-    if (lane == 0) s_w[wave] = pre;
-    __syncthreads();
-    if (t == 0) {
-        int x = 0;
-        for (int w = 0; w < kThreads / 64; ++w) x += s_w[w];
-        s_base = x;
-        if (blockIdx.x == gridDim.x - 1) b.CTR[CTR_S] = x + b.SELCNT[blockIdx.x];
-    }
-    __syncthreads();
-    int run = s_base;
+    int run = c0;
     for (int tb = c0; tb < c1; tb += kSelTile) {
         const int base = tb + t * kSelItems;
         uint32_t hit = base < c1 ? match16(b.NXT, base, c1, target) : 0u;
@@ -331,15 +310,39 @@ __global__ __launch_bounds__(kThreads) void k_sel_scatter(Bufs b, uint16_t targe
         while (hit) {
             const int i = __builtin_ctz(hit);
             hit &= hit - 1;
-            b.SPL[pos++] = base + i;
+            b.SPLX[pos++] = base + i;
         }
         run += total;
     }
+    if (t == 0) b.SELCNT[blockIdx.x] = run - c0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b) {
+    __shared__ int s_w[kThreads / 64];
+    __shared__ int s_base;
+    const int E = b.CTR[CTR_E];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int c0, c1;
+    sel_chunk(E, c0, c1);
+    int pre = 0;
+    for (int i = t; i < (int)blockIdx.x; i += kThreads) pre += b.SELCNT[i];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if (lane == 0) s_w[wave] = pre;
+    __syncthreads();
+    if (t == 0) {
+        int x = 0;
+        for (int w = 0; w < kThreads / 64; ++w) x += s_w[w];
+        s_base = x;
+        if (blockIdx.x == gridDim.x - 1) b.CTR[CTR_S] = x + b.SELCNT[blockIdx.x];
+    }
+    __syncthreads();
+    const int n = b.SELCNT[blockIdx.x], base = s_base;
+    for (int i = t; i < n; i += kThreads) b.SPL[base + i] = b.SPLX[c0 + i];
 }
 
 void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_count, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
-    hipLaunchKernelGGL(k_sel_scatter, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
+    hipLaunchKernelGGL(k_sel_local, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
+    hipLaunchKernelGGL(k_sel_gather, dim3(kSelBlocks), dim3(kThreads), 0, st, b);
 }
 
 // -------------------------------------------- steps 4-5a: split and keys

@@ -71,4 +71,9 @@ def test_prune_argument_errors(pcx):
     with pytest.raises(pcx.PcxError) as e:
         pcx.extract(m, box.lo, box.hi, include_output=True, prune=True, record_tape=True)
     assert e.value.code == pcx.PCX_ERR_INVALID
+    cx = pcx.extract(m, box.lo, box.hi, include_output=True, prune=True)
+    with pytest.raises(pcx.PcxError) as e:
+        cx.cell_counts()
+    assert e.value.code == pcx.PCX_ERR_INVALID
+    cx.close()
     m.close()
