@@ -227,9 +227,9 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                 __syncthreads();
             }
             if (N <= 32) block_split<32, 1>(b, g, V, E, S);
-            else if (N <= 64) block_split<64, 1>(b, g, V, E, S);
-            else if (N <= 128) block_split<64, 2>(b, g, V, E, S);
-            else block_split<64, 4>(b, g, V, E, S);
+            else if (N <= 64) block_split<32, 2>(b, g, V, E, S);
+            else if (N <= 128) block_split<32, 4>(b, g, V, E, S);
+            else block_split<32, 8>(b, g, V, E, S);
             __syncthreads();
             int np = 0;
             if (P > 0) np = block_pair(b, g, V, E + S, S * P, s_w);

@@ -288,7 +288,6 @@ struct GemmLds {
 template <int G, int NC>
 __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int e, int2 ab,
                                            int lane, int half) {
-    constexpr int wpc = G / 32;  // sign words per chunk
     const int D = g.D, Wd = g.Wd, ZS = g.ZS, j = g.j, N = g.Nl;
     const int nw = g.lw1 - g.lw0;
     const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;
@@ -312,8 +311,12 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     const double tt = zp / (zp - zq);
     const size_t x0 = (size_t)V0 + s;
     int bad = 0;
-    uint64_t pb[NC], nb[NC];
     double *Zo = b.Z + x0 * ZS;
+    // the layer's sign words of x0, one per 32 columns, built from the chunk
+    // ballots (both halves of the wave at once, on uniform values) and parked in
+    // LDS for the lane that owns the word below
+    __shared__ uint64_t s_codes[kThreads / 32][8];
+    const int grp = threadIdx.x / G;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
@@ -322,9 +325,21 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         const double z = (c == j) ? 0.0 : p + tt * (q - p);
         if (in && c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
         if (in && c >= g.zlo) Zo[c] = z;
-        pb[k] = __ballot(in && z > 0.0);
-        nb[k] = __ballot(in && z < 0.0);
+        const uint64_t pbk = __ballot(in && z > 0.0), nbk = __ballot(in && z < 0.0);
+        const uint64_t lo = codes_of((uint32_t)pbk, (uint32_t)nbk);
+        const uint64_t hi = codes_of((uint32_t)(pbk >> 32), (uint32_t)(nbk >> 32));
+        if (lane == 0) {
+            if (G == 64) {
+                s_codes[grp][2 * k] = lo;
+                s_codes[grp][2 * k + 1] = hi;
+            } else {
+                s_codes[grp][k] = half ? hi : lo;
+            }
+        }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double xp = apos ? xa : xb, xq = apos ? xb : xa;
     const double x0c = xp + tt * (xq - xp);
     // ---- sign row of x0, hash of the edge's sign-vector, zeros, next crossings.
@@ -351,19 +366,8 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         const uint64_t gt = live ? gt_mask(w, g.wn, g.bn, g.lw1) : 0ull;
         const uint64_t f = (wa | wb) & lt;
         if (f & (f >> 1) & 0x5555555555555555ull) bad |= FLAG_CONFLICT;
-        uint64_t cw = 0;
         const int u = w - g.lw0;
-        if (live && u >= 0 && u < nw) {
-            const int ku = u / wpc, sh = 32 * (wpc == 2 ? (u & 1) : half);
-            uint64_t P = 0, Q = 0;
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-                if (k == ku) {
-                    P = pb[k];
-                    Q = nb[k];
-                }
-            cw = codes_of((uint32_t)(P >> sh), (uint32_t)(Q >> sh));
-        }
+        const uint64_t cw = (live && u >= 0 && u < nw) ? s_codes[grp][u] : 0ull;
         const uint64_t rx = f | (cw & gt);
         if (it == 0) rx0 = rx;
         else if (live) b.SG[x0 * Wd + w] = rx;

@@ -375,18 +375,19 @@ __global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, 
 
 void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st) {
     if (S <= 0) return;
-    const int G = g.Nl > 32 ? 64 : 32;
-    const int groups = kThreads / G;
+    // two splits per wave (32-lane groups): the per-split bookkeeping on the
+    // sign words runs once for both halves of the wave
+    const int groups = kThreads / 32;
     int grid = (S + groups - 1) / groups;
     grid = grid > 16384 ? 16384 : grid;
-    if (G == 32)
+    if (g.Nl <= 32)
         hipLaunchKernelGGL((k_split<32, 1>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
     else if (g.Nl <= 64)
-        hipLaunchKernelGGL((k_split<64, 1>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 2>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
     else if (g.Nl <= 128)
-        hipLaunchKernelGGL((k_split<64, 2>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 4>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
     else
-        hipLaunchKernelGGL((k_split<64, 4>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 8>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
 }
 
 // ---------------------------------------------------- step 5b: radix sort
