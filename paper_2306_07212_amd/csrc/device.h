@@ -288,7 +288,12 @@ struct GemmLds {
 template <int G, int NC>
 __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int e, int2 ab,
                                            int lane, int half) {
-    const int D = g.D, Wd = g.Wd, ZS = g.ZS, j = g.j, N = g.Nl;
+    const int D = g.D, Wd = g.Wd, ZS = g.ZS;
+    // the per-column predicates below (c < N, c vs j, c >= zlo) are cheap to
+    // recompute; an empty asm makes their bounds opaque per split so that they
+    // are not hoisted out of the caller's loop into dozens of live lane masks
+    int j = g.j, N = g.Nl, zlo = g.zlo;
+    asm volatile("" : "+v"(j), "+v"(N), "+v"(zlo));
     const int nw = g.lw1 - g.lw0;
     const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;
     const uint64_t *Ra = b.SG + (size_t)ab.x * Wd, *Rb = b.SG + (size_t)ab.y * Wd;
@@ -298,7 +303,7 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
-        const bool live = c < N && c >= g.zlo;
+        const bool live = c < N && c >= zlo;
         A[k] = live ? Za[c] : 0.0;
         B[k] = live ? Zb[c] : 0.0;
     }
@@ -312,11 +317,11 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     const size_t x0 = (size_t)V0 + s;
     int bad = 0;
     double *Zo = b.Z + x0 * ZS;
-    // the layer's sign words of x0, one per 32 columns, built from the chunk
-    // ballots (both halves of the wave at once, on uniform values) and parked in
-    // LDS for the lane that owns the word below
-    __shared__ uint64_t s_codes[kThreads / 32][8];
-    const int grp = threadIdx.x / G;
+    // the chunk ballots of x0's pre-activations (which columns are +, which -),
+    // parked in LDS for the lane that owns the corresponding sign word below
+    __shared__ uint64_t s_pos[kThreads / 64][kMaxWidth / 32], s_neg[kThreads / 64][kMaxWidth / 32];
+    static_assert(G == 64 ? NC <= kMaxWidth / 64 : NC <= kMaxWidth / 32, "chunk ballots exceed the LDS slots");
+    const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
@@ -324,17 +329,11 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         const double p = apos ? A[k] : B[k], q = apos ? B[k] : A[k];
         const double z = (c == j) ? 0.0 : p + tt * (q - p);
         if (in && c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
-        if (in && c >= g.zlo) Zo[c] = z;
+        if (in && c >= zlo) Zo[c] = z;
         const uint64_t pbk = __ballot(in && z > 0.0), nbk = __ballot(in && z < 0.0);
-        const uint64_t lo = codes_of((uint32_t)pbk, (uint32_t)nbk);
-        const uint64_t hi = codes_of((uint32_t)(pbk >> 32), (uint32_t)(nbk >> 32));
-        if (lane == 0) {
-            if (G == 64) {
-                s_codes[grp][2 * k] = lo;
-                s_codes[grp][2 * k + 1] = hi;
-            } else {
-                s_codes[grp][k] = half ? hi : lo;
-            }
+        if ((threadIdx.x & 63) == 0) {
+            s_pos[wv][k] = pbk;
+            s_neg[wv][k] = nbk;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -367,7 +366,12 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         const uint64_t f = (wa | wb) & lt;
         if (f & (f >> 1) & 0x5555555555555555ull) bad |= FLAG_CONFLICT;
         const int u = w - g.lw0;
-        const uint64_t cw = (live && u >= 0 && u < nw) ? s_codes[grp][u] : 0ull;
+        uint64_t cw = 0;
+        if (live && u >= 0 && u < nw) {
+            // word u = chunk u / (G/32); inside the chunk's 64-bit ballot, this group's 32 columns
+            const int ku = G == 64 ? (u >> 1) : u, sh = G == 64 ? 32 * (u & 1) : 32 * half;
+            cw = codes_of((uint32_t)(s_pos[wv][ku] >> sh), (uint32_t)(s_neg[wv][ku] >> sh));
+        }
         const uint64_t rx = f | (cw & gt);
         if (it == 0) rx0 = rx;
         else if (live) b.SG[x0 * Wd + w] = rx;

@@ -365,7 +365,7 @@ void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
 // holds column k*G + c; the sign words of the layer come straight from the
 // chunk ballots (no LDS).
 template <int G, int NC>
-__global__ __launch_bounds__(kThreads) void k_split(Bufs b, StepGeom g, int V0, int E0, int S) {
+__global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g, int V0, int E0, int S) {
     constexpr int groups = kThreads / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
