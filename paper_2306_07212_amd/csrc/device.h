@@ -168,7 +168,7 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
     const uint64_t *Ra = b.SG + (size_t)xa * g.Wd, *Rb = b.SG + (size_t)xb * g.Wd;
     uint64_t diff = check_hash ? (b.FULL[sa] ^ b.FULL[sb]) : 0ull;
     // no early exit: the row loads of all words are independent and pipeline
-#pragma unroll 4
+#pragma unroll 8
     for (int w = 0; w <= g.wn; ++w) {
         const uint64_t lt = lt_mask(w, g.wn, g.bn);
         const uint64_t fa = (Ra[w] & lt) | (w == wa ? ca : 0ull);
@@ -176,9 +176,19 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
         diff |= fa ^ fb;
     }
     if (diff) raise_flag(b.CTR, FLAG_VERIFY);
+    // first crossing after the neuron: four words per round, loaded together
     int col = kNoCol;
-    for (int w = g.wn; w < g.lw1 && col == kNoCol; ++w)
-        col = first_col((Ra[w] ^ Rb[w]) & gt_mask(w, g.wn, g.bn, g.lw1), w, g.lw0);
+    for (int w0 = g.wn; w0 < g.lw1 && col == kNoCol; w0 += 4) {
+        uint64_t x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int w = w0 + i;
+            x[i] = w < g.lw1 ? (Ra[w] ^ Rb[w]) & gt_mask(w, g.wn, g.bn, g.lw1) : 0ull;
+        }
+#pragma unroll
+        for (int i = 3; i >= 0; --i)
+            if (x[i]) col = first_col(x[i], w0 + i, g.lw0);
+    }
     b.EDG[out] = make_int2(xa, xb);
     b.NXT[out] = col == kNoCol ? kNone : (uint16_t)col;
 }

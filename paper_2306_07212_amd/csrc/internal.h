@@ -38,7 +38,7 @@ struct HEntry {
     unsigned long long key;
     uint32_t a, b;
 };
-constexpr int kPairItems = 4;  // key slots per thread in the hash pairing passes
+constexpr int kPairItems = 4;  // hash pairing: chunk granularity of the passes, key slots per thread in the batched kernel
 
 enum { PAIR_HASH = 0, PAIR_SORT = 1 };
 

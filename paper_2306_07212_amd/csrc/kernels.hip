@@ -588,16 +588,13 @@ __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g, in
     int c0, c1;
     pair_chunk(nslots, c0, c1);
     int cnt = 0;
-    for (int base = c0 + threadIdx.x * kPairItems; base < c1; base += kThreads * kPairItems)
-#pragma unroll
-        for (int i = 0; i < kPairItems; ++i) {
-            const int u = base + i;
-            if (u >= c1) break;
-            int partner = -1;
-            const bool own = hash_owner(b, g, u, nslots, partner);
-            b.PART[u] = own ? partner : -1;
-            cnt += own;
-        }
+    // one slot per thread: the table probe is a chain of dependent loads
+    for (int u = c0 + (int)threadIdx.x; u < c1; u += kThreads) {
+        int partner = -1;
+        const bool own = hash_owner(b, g, u, nslots, partner);
+        b.PART[u] = own ? partner : -1;
+        cnt += own;
+    }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
     __syncthreads();
@@ -638,24 +635,15 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int
     }
     __syncthreads();
     int run = s_base;
-    for (int tb = c0; tb < c1; tb += kThreads * kPairItems) {
-        const int base = tb + t * kPairItems;
-        int partner[kPairItems];
-        uint32_t own = 0;
-#pragma unroll
-        for (int i = 0; i < kPairItems; ++i) {
-            partner[i] = base + i < c1 ? b.PART[base + i] : -1;
-            if (partner[i] >= 0) own |= 1u << i;
-        }
-        const int cnt = __popc(own);
-        int incl = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
-        }
-        __syncthreads();
-        if (lane == 63) s_w[wave] = incl;
+    // one slot per thread: an owner's edge is a chain of dependent row loads,
+    // so owners are spread over as many threads as possible rather than queued
+    // behind each other in one thread
+    for (int tb = c0; tb < c1; tb += kThreads) {
+        const int u = tb + t;
+        const int partner = u < c1 ? b.PART[u] : -1;
+        const uint64_t m = __ballot(partner >= 0);
+        __syncthreads();  // s_w of the previous round has been read
+        if (lane == 0) s_w[wave] = __popcll(m);
         __syncthreads();
         int wave_off = 0, total = 0;
 #pragma unroll
@@ -664,10 +652,10 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int
             if (w < wave) wave_off += ws;
             total += ws;
         }
-        int pos = run + wave_off + incl - cnt;
-#pragma unroll
-        for (int i = 0; i < kPairItems; ++i)
-            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++, false);
+        if (partner >= 0) {
+            const int pos = run + wave_off + __popcll(m & ((1ull << lane) - 1ull));
+            emit_pair(b, g, V0, nslots, u, partner, (size_t)E1 + pos, false);
+        }
         run += total;
     }
 }
