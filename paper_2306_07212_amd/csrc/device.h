@@ -28,20 +28,22 @@ __device__ __forceinline__ uint64_t word_hash(int w, uint64_t v) {
     return mix64(v + (uint64_t)(w + 1) * 0x9e3779b97f4a7c15ull);
 }
 
-// spread the 32 bits of x to the even bit positions of a 64-bit word
-__device__ __forceinline__ uint64_t part1by1(uint32_t x) {
-    uint64_t v = x;
-    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
-    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
-    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    v = (v | (v << 2)) & 0x3333333333333333ull;
-    v = (v | (v << 1)) & 0x5555555555555555ull;
-    return v;
+// spread the 16 low bits of x to the even bit positions of a 32-bit word
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
 }
 
-// 2-bit codes of 32 entries from their positive / negative masks
+// 2-bit codes of 32 entries from their positive / negative masks (entry i at
+// bits 2i, 2i+1: 01 positive, 10 negative, 00 zero)
 __device__ __forceinline__ uint64_t codes_of(uint32_t pos, uint32_t neg) {
-    return part1by1(pos) | (part1by1(neg) << 1);
+    const uint32_t lo = spread16(pos) | (spread16(neg) << 1);
+    const uint32_t hi = spread16(pos >> 16) | (spread16(neg >> 16) << 1);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // entries strictly before entry n = (wn, bn) inside word w
@@ -303,7 +305,7 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     // recompute; an empty asm makes their bounds opaque per split so that they
     // are not hoisted out of the caller's loop into dozens of live lane masks
     int j = g.j, N = g.Nl, zlo = g.zlo;
-    asm volatile("" : "+v"(j), "+v"(N), "+v"(zlo));
+    asm volatile("" : "+s"(j), "+s"(N), "+s"(zlo));
     const int nw = g.lw1 - g.lw0;
     const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;
     const uint64_t *Ra = b.SG + (size_t)ab.x * Wd, *Rb = b.SG + (size_t)ab.y * Wd;
@@ -328,24 +330,27 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     int bad = 0;
     double *Zo = b.Z + x0 * ZS;
     // the chunk ballots of x0's pre-activations (which columns are +, which -),
-    // parked in LDS for the lane that owns the corresponding sign word below
-    __shared__ uint64_t s_pos[kThreads / 64][kMaxWidth / 32], s_neg[kThreads / 64][kMaxWidth / 32];
+    // parked in LDS for the lane that owns the corresponding sign word below.
+    // Lanes outside [zlo, N) hold A = B = 0, so their z is exactly 0 and they
+    // add no bit to either ballot. Column j is interpolated like the others:
+    // every use of its ballot bits below is masked to the entries after j, and
+    // its stored value is overwritten by an exact 0.
+    __shared__ uint64_t s_bal[kThreads / 64][kMaxWidth / 32][2];
     static_assert(G == 64 ? NC <= kMaxWidth / 64 : NC <= kMaxWidth / 32, "chunk ballots exceed the LDS slots");
     const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const int c = k * G + lane;
-        const bool in = c < N;
         const double p = apos ? A[k] : B[k], q = apos ? B[k] : A[k];
-        const double z = (c == j) ? 0.0 : p + tt * (q - p);
-        if (in && c > j && z == 0.0) bad |= FLAG_ZERO_SIGN;
-        if (in && c >= zlo) Zo[c] = z;
-        const uint64_t pbk = __ballot(in && z > 0.0), nbk = __ballot(in && z < 0.0);
+        const double z = p + tt * (q - p);
+        if (c < N && c >= zlo) Zo[c] = z;
+        const uint64_t pbk = __ballot(z > 0.0), nbk = __ballot(z < 0.0);
         if ((threadIdx.x & 63) == 0) {
-            s_pos[wv][k] = pbk;
-            s_neg[wv][k] = nbk;
+            s_bal[wv][k][0] = pbk;
+            s_bal[wv][k][1] = nbk;
         }
     }
+    if (lane == (j & (G - 1)) && j >= zlo) Zo[j] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -375,18 +380,21 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         const uint64_t gt = live ? gt_mask(w, g.wn, g.bn, g.lw1) : 0ull;
         const uint64_t f = (wa | wb) & lt;
         if (f & (f >> 1) & 0x5555555555555555ull) bad |= FLAG_CONFLICT;
+        const uint64_t vw = live ? b.VALID[w] : 0ull;
         const int u = w - g.lw0;
         uint64_t cw = 0;
         if (live && u >= 0 && u < nw) {
             // word u = chunk u / (G/32); inside the chunk's 64-bit ballot, this group's 32 columns
             const int ku = G == 64 ? (u >> 1) : u, sh = G == 64 ? 32 * (u & 1) : 32 * half;
-            cw = codes_of((uint32_t)(s_pos[wv][ku] >> sh), (uint32_t)(s_neg[wv][ku] >> sh));
+            cw = codes_of((uint32_t)(s_bal[wv][ku][0] >> sh), (uint32_t)(s_bal[wv][ku][1] >> sh));
+            // an exact zero at a later neuron of the layer: x0 lies on two hyperplanes
+            if (~(cw | (cw >> 1)) & vw & gt) bad |= FLAG_ZERO_SIGN;
         }
         const uint64_t rx = f | (cw & gt);
         if (it == 0) rx0 = rx;
         else if (live) b.SG[x0 * Wd + w] = rx;
         if (live && w <= g.wn) hsum += word_hash(w, f);
-        const uint64_t zm = live ? (~(f | (f >> 1)) & b.VALID[w] & lt) : 0ull;
+        const uint64_t zm = ~(f | (f >> 1)) & vw & lt;
         const int zc = __popcll(zm);
         uint64_t has = (__ballot(zc != 0) >> gshift) & gmask;
         int srcl = lane;

@@ -125,6 +125,19 @@ def test_degenerate_input_is_reported(oracle_lib, pcx):
         oracle_lib.extract(net, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
 
 
+def test_vertex_on_two_hyperplanes_is_reported(oracle_lib, pcx):
+    """A new vertex that lands exactly on a later neuron's hyperplane is not
+    generic either: x = 0.5 cuts the bottom edge at (0.5, -1), where the
+    second neuron x + y + 0.5 interpolates to exactly 0 (Sec. 3.2)."""
+    net = wl.Net([2, 2, 1], [np.array([[1.0, 0.0], [1.0, 1.0]]), np.array([[1.0, 1.0]])],
+                 [np.array([-0.5, 0.5]), np.array([0.0])])
+    with pytest.raises(pcx.PcxError) as e:
+        gpu_complex(pcx, net, wl.cube(2))
+    assert e.value.code == pcx.PCX_ERR_DEGENERATE
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.extract(net, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
+
+
 def test_invalid_arguments(pcx):
     net = wl.plain_small()
     m = pcx.MLP.from_net(net)

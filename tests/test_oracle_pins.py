@@ -446,3 +446,24 @@ def test_cell_mistakes_are_caught(oracle_lib, mutation):
         f, _ = face_counts(r.S, r.edges, widths[0], m, mutation=mutation)
         bad |= sum((-1) ** k * x for k, x in enumerate(f)) != 1
     assert bad
+
+
+@pytest.mark.parametrize("which", ["corner", "new_vertex"])
+def test_non_generic_inputs_are_rejected(oracle_lib, which):
+    """Sec. 3.2 assumes general position: a hyperplane through box corners,
+    or a new vertex that lies exactly on a later hyperplane, is reported
+    instead of producing a complex with a vertex of too many zeros."""
+    if which == "corner":
+        net = wl.Net([2, 1, 1], [np.array([[1.0, 1.0]]), np.array([[1.0]])], [np.array([0.0]), np.array([0.0])])
+    else:
+        net = wl.Net([2, 2, 1], [np.array([[1.0, 0.0], [1.0, 1.0]]), np.array([[1.0, 1.0]])],
+                     [np.array([-0.5, 0.5]), np.array([0.0])])
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.extract(net, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
+    # moving the second hyperplane off the vertex makes the input generic again
+    if which == "new_vertex":
+        ok = wl.Net([2, 2, 1], [np.array([[1.0, 0.0], [1.0, 1.0]]), np.array([[1.0, 1.0]])],
+                    [np.array([-0.5, 0.25]), np.array([0.0])])
+        r = oracle_lib.extract(ok, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
+        # two lines crossing inside the square cut it into 4 regions: V - E + F = 1
+        assert len(r.X) - len(r.edges) + 4 == 1
