@@ -1,8 +1,9 @@
 // Host side of libpcx.so: the C ABI of include/pcx.h and the orchestration of
 // edge subdivision (Berzins 2023, Sec. 4.2) on one GPU. Weights are copied to
-// the device once per network; an extraction keeps every array on the device
-// and crosses to the host once per neuron step to read four counters (the
-// number of splitting edges sizes the launches and the storage).
+// the device once per network; an extraction keeps every array on the device.
+// With hash pairing the kernels of a neuron step take their counts from device
+// counters, so the host queues steps ahead and reads the counters only every
+// few steps (to grow the storage ahead of the complex) and at layer starts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,18 +72,40 @@ struct Extraction {
     int pair_mode = PAIR_HASH;
     HEntry *HT[2] = {nullptr, nullptr};  // 2-face hash tables, alternating by step
     size_t Tcap = 0;                     // entries per table
-    uint32_t Tused[2] = {0, 0};          // entries a step left to clear
-    int hparity = 0;
     bool tape = false;
     bool prune = false;
     int D = 0, Wd = 0, ZS = 0, P = 0;
-    int *hctr = nullptr;  // pinned
+    int *hctr = nullptr;     // pinned: the counters after a drain
+    int *hsnap[2] = {};      // pinned: counter snapshots taken ahead of the host
+    hipEvent_t evsnap[2] = {};
+    int snap_at[2] = {-1, -1};  // step before which each pending snapshot was taken
+    int snap_next = 0;
+    bool tables_reset = false;  // the hash tables were reallocated (zeroed)
     EventPool ev;
     double ktime[PCX_K_COUNT] = {};
     int64_t klaunch[PCX_K_COUNT] = {};
 
     ~Extraction() {
         if (hctr) (void)hipHostFree(hctr);
+        for (int i = 0; i < 2; ++i) {
+            if (hsnap[i]) (void)hipHostFree(hsnap[i]);
+            if (evsnap[i]) (void)hipEventDestroy(evsnap[i]);
+        }
+    }
+
+    // every enqueued kernel done; hctr = the device counters
+    int drain() {
+        HIPCHK(hipMemcpyAsync(hctr, b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        snap_at[0] = snap_at[1] = -1;
+        return collect();
+    }
+    // set one device counter (between drains: nothing else is in flight)
+    int put_ctr(int idx, int v) {
+        hctr[idx] = v;
+        HIPCHK(hipMemcpyAsync(b.CTR + idx, hctr + idx, sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return PCX_OK;
     }
 
     int mark(int fam, bool start) {
@@ -193,9 +216,9 @@ struct Extraction {
                 for (int t = 0; t < 2; ++t) {
                     if ((rc = grow_scratch(HT[t], Tcap, tc))) return rc;
                     HIPCHK(hipMemsetAsync(HT[t], 0, tc * sizeof(HEntry), st));
-                    Tused[t] = 0;
                 }
                 Tcap = tc;
+                tables_reset = true;
             }
             return PCX_OK;
         }
@@ -242,31 +265,23 @@ int future_signs(Extraction &x, const pcx_mlp *mlp, int l, int nsub, int64_t V, 
 }
 
 // Drop the edges whose vertices agree on every sign word from lwf on, then the
-// vertices left without an edge; survivors keep their order.
-int prune_now(Extraction &x, int64_t &V, int64_t &E, int lwf, int64_t &E_before) {
-    E_before = E;
+// vertices left without an edge; survivors keep their order. V, E are the
+// exact counts (after a drain); the new ones go to the counters of parity par.
+int prune_now(Extraction &x, int64_t &V, int64_t &E, int lwf, int par) {
     if (V == 0) return PCX_OK;
     hipStream_t st = x.st;
     void *pm, *pmap, *pe, *px, *ps, *pz;
     int rc;
-    // the host learns the edge count only at each step's compaction: take the
-    // count the last step's pairing left on the device
-    HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
-    E = x.hctr[CTR_E];
-    E_before = E;
     if ((rc = x.arena.alloc(&pm, (size_t)V))) return rc;
     if ((rc = x.arena.alloc(&pmap, (size_t)V * sizeof(int)))) return rc;
     if ((rc = x.arena.alloc(&pe, x.Ecap * sizeof(int2)))) return rc;
     HIPCHK(hipMemsetAsync(pm, 0, (size_t)V, st));
-    launch_prune_edges(x.b, (int)V, (int)E, x.Wd, lwf, (int2 *)pe, (uint8_t *)pm, st);
-    launch_prune_vertices(x.b, (int)V, (const uint8_t *)pm, (int *)pmap, st);
+    launch_prune_edges(x.b, (int)V, (int)E, x.Wd, lwf, (int2 *)pe, (uint8_t *)pm, par, st);
+    launch_prune_vertices(x.b, (int)V, (const uint8_t *)pm, (int *)pmap, par, st);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if ((rc = x.drain())) return rc;
     if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
-    const int64_t Vn = x.hctr[CTR_V], En = x.hctr[CTR_E];
+    const int64_t Vn = x.hctr[CTR_V + par], En = x.hctr[CTR_E + par];
     if ((rc = x.arena.alloc(&px, x.Vcap * (size_t)x.D * sizeof(double)))) return rc;
     if ((rc = x.arena.alloc(&ps, x.Vcap * (size_t)x.Wd * sizeof(uint64_t)))) return rc;
     if ((rc = x.arena.alloc(&pz, x.Vcap * (size_t)x.ZS * sizeof(double)))) return rc;
@@ -426,6 +441,10 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     const bool box = dom.lo != nullptr;
     const size_t V0 = box ? (size_t)1 << D : dom.W0.size(), E0 = box ? (size_t)D << (D - 1) : dom.E0.size();
     HIPCHK(hipHostMalloc((void **)&x.hctr, CTR_COUNT * sizeof(int), hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipHostMalloc((void **)&x.hsnap[i], CTR_COUNT * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&x.evsnap[i], hipEventDisableTiming));
+    }
     {
         void *p;
         if ((rc = x.arena.alloc(&p, CTR_COUNT * sizeof(int)))) return rc;
@@ -448,7 +467,9 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     if ((rc = x.ensure_edges(std::max<size_t>({E0, 4096, (size_t)mlp->hintE.load()}), 0, 0))) return rc;
     {
         int h[CTR_COUNT] = {0};
+        h[CTR_V] = (int)V0;
         h[CTR_E] = (int)E0;
+        h[CTR_FAIL] = 0x7fffffff;
         std::memcpy(x.hctr, h, sizeof h);
         HIPCHK(hipMemcpyAsync(x.b.CTR, x.hctr, sizeof h, hipMemcpyHostToDevice, st));
     }
@@ -478,137 +499,269 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     HIPCHK(hipGetLastError());
 
     std::vector<int64_t> steps((size_t)n_steps * 4, 0);
+    std::vector<int> step0(nsub + 1, 0);
+    for (int l = 0; l < nsub; ++l) step0[l + 1] = step0[l] + mlp->widths[l + 1];
+    if (n_steps > 0) {
+        void *p;
+        if ((rc = x.arena.alloc(&p, (size_t)n_steps * sizeof(StepRec)))) return rc;
+        x.b.REC = (StepRec *)p;
+    }
+    // Hash pairing runs ahead of the host: every count a kernel needs is on the
+    // device, and the host looks at the counters every kAhead steps (a
+    // snapshot taken kAhead steps earlier, so the queue never runs dry). A step
+    // that finds the storage too small writes nothing, every later kernel
+    // returns at once, and the host grows the storage (geometrically, from the
+    // exact counts) and redoes that step. The storage starts at the sizes of
+    // the network's earlier extractions, so a repeated extraction never grows.
+    // Sort pairing sizes its radix sort on the host and reads the counters at
+    // every step.
+    const bool lagged = x.pair_mode == PAIR_HASH;
+    constexpr int kAhead = 8;
+    const int64_t Shint = std::min<int64_t>(mlp->hintS.load(), (int64_t)x.Scap);
+    if ((rc = x.ensure_step((size_t)Shint, (size_t)Shint * x.P))) return rc;
+    x.tables_reset = false;  // new tables are zero, and so are the counters
     int64_t V = (int64_t)V0, E = (int64_t)E0;
-    int64_t prevE = -1, prevS = 0;
-    bool k_recorded = false;  // the previous step's pair count was taken before a pruning
-    int step = 0;
-    int64_t total_splits = 0;
+    int64_t Sgrid = 64;  // split count the split launch is shaped for (any count is covered)
+    int64_t prevE = -1, prevS = 0;  // sort pairing: the host's own step log
+    bool pairs_logged = false;      //   the previous step's pair count was taken at a layer start
     const char *verbose_env = getenv("PCX_VERBOSE");
     const bool verbose = verbose_env && verbose_env[0] == '1';
-    for (int l = 0; l < nsub; ++l) {
-        const int N = mlp->widths[l + 1], K = mlp->widths[l];
-        if (verbose) {
-            fprintf(stderr, "[pcx] layer %d start: V=%lld E<=%lld device bytes=%llu peak=%llu\n", l + 1, (long long)V,
-                    (long long)(E + prevS * D), (unsigned long long)x.arena.cur, (unsigned long long)x.arena.peak);
-            fflush(stderr);
+    int redone = 0;
+
+    // grow the storage for `ahead` more steps of up to Sx splits each from the
+    // exact counts Vx, Ex (after a drain); spl_used: split ids the current
+    // step's compaction already wrote (kept)
+    auto grow_for = [&](int64_t Vx, int64_t Ex, int64_t Sx, int ahead, size_t spl_used = 0) -> int {
+        int r;
+        const int64_t Vneed = Vx + (int64_t)ahead * Sx, Eneed = Ex + (int64_t)ahead * Sx * std::max(1, D);
+        if (Vneed >= INT32_MAX || Eneed >= INT32_MAX)
+            return fail(PCX_ERR_CAPACITY, "complex exceeds 2^31 vertices or edges");
+        if ((r = x.ensure_vertices((size_t)Vneed, (size_t)Vx))) return r;
+        if ((r = x.ensure_edges((size_t)Eneed, (size_t)Ex, spl_used))) return r;
+        if ((r = x.ensure_step((size_t)Sx, (size_t)Sx * x.P))) return r;
+        if (x.tables_reset) {
+            x.tables_reset = false;
+            if ((r = x.put_ctr(CTR_TUSED, 0)) || (r = x.put_ctr(CTR_TUSED + 1, 0))) return r;
         }
-        // step 1 for the whole layer: pre-activations at every vertex
-        if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
-        if (l == 0) {
-            launch_gemm(x.b, ZS, x.b.X, D, 0, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
-        } else if (x.tape) {
-            // keep the previous layer's rows: evaluate into a fresh buffer
-            double *prev = x.b.Z;
-            void *q;
-            if ((rc = x.arena.alloc(&q, x.Vcap * (size_t)ZS * sizeof(double)))) return rc;
-            tapeZ.push_back(prev);
-            x.b.Z = (double *)q;
-            launch_gemm(x.b, ZS, prev, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
-        } else {
-            launch_gemm(x.b, ZS, x.b.Z, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
-        }
-        if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
-        if (x.prune) {
+        return PCX_OK;
+    };
+    // after a drain: a step that found the storage too small is redone from its
+    // compaction once the storage fits it; returns that step, or -1
+    auto recover = [&](int &fstep) -> int {
+        fstep = -1;
+        const int flags = x.hctr[CTR_FLAGS];
+        if (!flags) return PCX_OK;
+        if (flags != FLAG_CAPACITY) return degenerate_message(flags & ~FLAG_CAPACITY);
+        const int f = x.hctr[CTR_FAIL];
+        if (f < 0 || f >= n_steps) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
+        const int64_t Sf = x.hctr[CTR_S], Vf = x.hctr[CTR_V + (f & 1)], Ef = x.hctr[CTR_E + (f & 1)];
+        int r;
+        // exactly what step f needs: each array that is short grows by half
+        if ((r = grow_for(Vf, Ef, Sf, 1))) return r;
+        if ((r = x.put_ctr(CTR_FAIL, 0x7fffffff)) || (r = x.put_ctr(CTR_FLAGS, 0))) return r;
+        fstep = f;
+        ++redone;
+        return PCX_OK;
+    };
+
+    int l = 0, j = 0;
+    bool started = false;
+    while (true) {
+        if (!started) {
+            // layer start (or the end): every enqueued step is done
+            if ((rc = x.drain())) return rc;
+            int f;
+            if ((rc = recover(f))) return rc;
+            if (f >= 0) {
+                // the failed step belongs to the layer just finished
+                l = (int)(std::upper_bound(step0.begin(), step0.end(), f) - step0.begin()) - 1;
+                j = f - step0[l];
+                started = true;
+                continue;
+            }
+            if (l == nsub) break;
+            const int par0 = step0[l] & 1;
+            V = x.hctr[CTR_V + par0];
+            E = x.hctr[CTR_E + par0];
+            // launch shape from the previous step's count until this layer's own largest is known
+            const int64_t Slast = step0[l] > 0 ? x.hctr[CTR_S] : 0;
+            Sgrid = Slast + Slast / 4 + 64;
+            if (lagged && (rc = x.put_ctr(CTR_SMAX, 0))) return rc;
+            if (!lagged && step0[l] > 0) {
+                // before pruning can change the edge count
+                steps[(size_t)(step0[l] - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+                pairs_logged = true;
+            }
+            const int N = mlp->widths[l + 1], K = mlp->widths[l];
+            if (verbose) {
+                fprintf(stderr, "[pcx] layer %d start: V=%lld E=%lld device bytes=%llu peak=%llu\n", l + 1,
+                        (long long)V, (long long)E, (unsigned long long)x.arena.cur,
+                        (unsigned long long)x.arena.peak);
+                fflush(stderr);
+            }
+            // step 1 for the whole layer: pre-activations at every vertex
             if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
-            if ((rc = future_signs(x, mlp, l, nsub, V, lw))) return rc;
+            if (l == 0) {
+                launch_gemm(x.b, ZS, x.b.X, D, 0, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+            } else if (x.tape) {
+                // keep the previous layer's rows: evaluate into a fresh buffer
+                double *prev = x.b.Z;
+                void *q;
+                if ((rc = x.arena.alloc(&q, x.Vcap * (size_t)ZS * sizeof(double)))) return rc;
+                tapeZ.push_back(prev);
+                x.b.Z = (double *)q;
+                launch_gemm(x.b, ZS, prev, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+            } else {
+                launch_gemm(x.b, ZS, x.b.Z, ZS, 1, (int)V, K, N, mlp->Wt[l], mlp->b[l], Wd, lw[l], st);
+            }
             if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
+            if (x.prune) {
+                if ((rc = x.mark(PCX_K_GEMM, true))) return rc;
+                if ((rc = future_signs(x, mlp, l, nsub, V, lw))) return rc;
+                if ((rc = x.mark(PCX_K_GEMM, false))) return rc;
+                if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
+                if ((rc = prune_now(x, V, E, lw[l], par0))) return rc;
+                if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
+            }
             if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
-            int64_t Epre = E;
-            if ((rc = prune_now(x, V, E, lw[l], Epre))) return rc;
-            // the previous step's pair count, from the edge count before pruning
-            if (step > 0) steps[(size_t)(step - 1) * 4 + 3] = 2 * (Epre - prevE - prevS);
-            k_recorded = true;
+            launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, par0, st);
             if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
-        }
-        if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
-        launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, st);
-        if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
-        HIPCHK(hipGetLastError());
-        for (int j = 0; j < N; ++j, ++step) {
-            if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-            launch_select(x.b, (uint16_t)j, st);
-            if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            if ((rc = x.collect())) return rc;
+            started = true;
+            j = 0;
+        }
+        const int N = mlp->widths[l + 1];
+        if (j == N) {
+            ++l;
+            started = false;
+            continue;
+        }
+        const int s = step0[l] + j, par = s & 1;
+        int blocks;
+        if (lagged) {
+            if (j % kAhead == 0) {
+                // snapshot before this step; read the one taken kAhead steps ago
+                const int slot = x.snap_next, other = slot ^ 1;
+                HIPCHK(hipMemcpyAsync(x.hsnap[slot], x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipEventRecord(x.evsnap[slot], st));
+                x.snap_at[slot] = s;
+                x.snap_next = other;
+                if (x.snap_at[other] >= 0) {
+                    HIPCHK(hipEventSynchronize(x.evsnap[other]));
+                    const int *c = x.hsnap[other];
+                    x.snap_at[other] = -1;
+                    Sgrid = std::max<int64_t>(Sgrid, c[CTR_SMAX] + c[CTR_SMAX] / 4 + 64);
+                    if (c[CTR_FLAGS]) {
+                        // stop running ahead: exact counts, then redo or report
+                        if ((rc = x.drain())) return rc;
+                        int f;
+                        if ((rc = recover(f))) return rc;
+                        if (f >= 0) {
+                            if (f < step0[l] || f > s) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
+                            j = f - step0[l];
+                            continue;
+                        }
+                    }
+                }
+            }
+            blocks = split_blocks((int)std::min<int64_t>(Sgrid, INT32_MAX), N);
+        }
+        StepGeom g;
+        g.D = D;
+        g.Wd = Wd;
+        g.ZS = ZS;
+        g.Nl = N;
+        g.lw0 = lw[l];
+        g.lw1 = lw[l + 1];
+        g.j = j;
+        g.wn = lw[l] + (j >> 5);
+        g.bn = 2 * (j & 31);
+        g.P = x.P;
+        // in the last subdivided layer nothing reads the processed columns again
+        g.zlo = (l == nsub - 1 && !x.tape) ? j + 1 : 0;
+        g.pair_mode = x.pair_mode;
+        g.hmask = 0;
+        g.HT = x.HT[par];
+        g.HTo = x.HT[par ^ 1];
+        g.step = s;
+        g.par = par;
+        if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
+        launch_select(x.b, (uint16_t)j, par, st);
+        if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
+        HIPCHK(hipGetLastError());
+        int64_t S = 0;
+        if (!lagged) {
+            if ((rc = x.drain())) return rc;
             if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
-            const int64_t S = x.hctr[CTR_S];
-            E = x.hctr[CTR_E];
-            if (step > 0 && !k_recorded) steps[(size_t)(step - 1) * 4 + 3] = 2 * (E - prevE - prevS);
-            k_recorded = false;
-            steps[(size_t)step * 4 + 0] = V;
-            steps[(size_t)step * 4 + 1] = E;
-            steps[(size_t)step * 4 + 2] = S;
+            S = x.hctr[CTR_S];
+            E = x.hctr[CTR_E + par];
+            V = x.hctr[CTR_V + par];
+            if (s > 0 && !pairs_logged) steps[(size_t)(s - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+            pairs_logged = false;
+            steps[(size_t)s * 4 + 0] = V;
+            steps[(size_t)s * 4 + 1] = E;
+            steps[(size_t)s * 4 + 2] = S;
             prevE = E;
             prevS = S;
-            if (S == 0) continue;
-            const int64_t Eneed = E + S + S * std::max(0, D - 1);
-            if (V + S >= INT32_MAX || Eneed >= INT32_MAX)
-                return fail(PCX_ERR_CAPACITY, "complex exceeds 2^31 vertices or edges");
-            if ((rc = x.ensure_vertices((size_t)(V + S), (size_t)V))) return rc;
-            if ((rc = x.ensure_edges((size_t)Eneed, (size_t)E, (size_t)S))) return rc;
-            if ((rc = x.ensure_step((size_t)S, (size_t)S * x.P))) return rc;
-            StepGeom g;
-            g.D = D;
-            g.Wd = Wd;
-            g.ZS = ZS;
-            g.Nl = N;
-            g.lw0 = lw[l];
-            g.lw1 = lw[l + 1];
-            g.j = j;
-            g.wn = lw[l] + (j >> 5);
-            g.bn = 2 * (j & 31);
-            g.P = x.P;
-            // in the last subdivided layer nothing reads the processed columns again
-            g.zlo = (l == nsub - 1 && !x.tape) ? j + 1 : 0;
-            g.pair_mode = x.pair_mode;
-            g.HT = nullptr;
-            g.hmask = 0;
-            uint32_t tsz = 256;
-            if (x.P > 0 && x.pair_mode == PAIR_HASH) {
-                while (tsz < 2 * (uint64_t)S * x.P) tsz <<= 1;
-                g.HT = x.HT[x.hparity];
-                g.hmask = tsz - 1;
-            }
-            if ((rc = x.mark(PCX_K_SPLIT, true))) return rc;
-            launch_split(x.b, g, (int)V, (int)E, (int)S, st);
-            if ((rc = x.mark(PCX_K_SPLIT, false))) return rc;
-            HIPCHK(hipGetLastError());
-            if (x.P > 0 && x.pair_mode == PAIR_HASH) {
-                if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
-                const int other = x.hparity ^ 1;
-                launch_hash_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), x.HT[other], x.Tused[other], st);
-                if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
-                HIPCHK(hipGetLastError());
-                x.Tused[other] = 0;
-                x.Tused[x.hparity] = tsz;
-                x.hparity = other;
-            } else if (x.P > 0) {
-                if ((rc = x.mark(PCX_K_SORT, true))) return rc;
-                launch_sort(x.b, (int)(S * x.P), st);
-                if ((rc = x.mark(PCX_K_SORT, false))) return rc;
-                HIPCHK(hipGetLastError());
-                if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
-                launch_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), st);
-                if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
-                HIPCHK(hipGetLastError());
-            } else {
-                x.hctr[CTR_E] = (int)(E + S);
-                HIPCHK(hipMemcpyAsync(x.b.CTR + CTR_E, x.hctr + CTR_E, sizeof(int), hipMemcpyHostToDevice, st));
-                HIPCHK(hipStreamSynchronize(st));
-            }
-            V += S;
-            total_splits += S;
+            if ((rc = grow_for(V, E, S, 1, (size_t)S))) return rc;
+            blocks = split_blocks((int)S, N);
         }
+        g.Vcap = (int)std::min<size_t>(x.Vcap, INT32_MAX);
+        g.Ecap = (int)std::min<size_t>(x.Ecap, INT32_MAX);
+        g.Kcap = (int)std::min<size_t>(x.Kcap, INT32_MAX);
+        if ((rc = x.mark(PCX_K_SPLIT, true))) return rc;
+        launch_split(x.b, g, blocks, st);
+        if ((rc = x.mark(PCX_K_SPLIT, false))) return rc;
+        HIPCHK(hipGetLastError());
+        if (lagged) {
+            if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
+            launch_hash_pair(x.b, g, st);
+            if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
+            HIPCHK(hipGetLastError());
+        } else if (S * x.P > 0) {
+            if ((rc = x.mark(PCX_K_SORT, true))) return rc;
+            launch_sort(x.b, (int)(S * x.P), st);
+            if ((rc = x.mark(PCX_K_SORT, false))) return rc;
+            HIPCHK(hipGetLastError());
+            if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
+            launch_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), st);
+            if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
+            HIPCHK(hipGetLastError());
+        } else {
+            if ((rc = x.put_ctr(CTR_E + (par ^ 1), (int)(E + S)))) return rc;
+        }
+        ++j;
     }
     HIPCHK(hipEventRecord(t1, st));
-    HIPCHK(hipMemcpyAsync(x.hctr, x.b.CTR, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if ((rc = x.collect())) return rc;
+    if ((rc = x.drain())) return rc;
     if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
-    E = x.hctr[CTR_E];
-    if (step > 0) steps[(size_t)(step - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+    V = x.hctr[CTR_V + (n_steps & 1)];
+    E = x.hctr[CTR_E + (n_steps & 1)];
+    int64_t total_splits = 0, Smax = 0;
+    if (lagged && n_steps > 0) {
+        std::vector<StepRec> rec(n_steps);
+        HIPCHK(hipMemcpy(rec.data(), x.b.REC, n_steps * sizeof(StepRec), hipMemcpyDeviceToHost));
+        for (int t = 0; t < n_steps; ++t) {
+            steps[(size_t)t * 4 + 0] = rec[t].V0;
+            steps[(size_t)t * 4 + 1] = rec[t].E0;
+            steps[(size_t)t * 4 + 2] = rec[t].S;
+            steps[(size_t)t * 4 + 3] = 2 * ((int64_t)rec[t].E1 - rec[t].E0 - rec[t].S);
+        }
+    } else if (n_steps > 0 && !pairs_logged) {
+        steps[(size_t)(n_steps - 1) * 4 + 3] = 2 * (E - prevE - prevS);
+    }
+    int64_t Ebound = E;  // the most edges any step's storage check asked for
+    for (int t = 0; t < n_steps; ++t) {
+        const int64_t St = steps[(size_t)t * 4 + 2];
+        total_splits += St;
+        Smax = std::max<int64_t>(Smax, St);
+        Ebound = std::max<int64_t>(Ebound, steps[(size_t)t * 4 + 1] + St * std::max(1, D));
+    }
+    if (verbose) {
+        fprintf(stderr, "[pcx] done: V=%lld E=%lld steps redone after growing the storage: %d\n", (long long)V,
+                (long long)E, redone);
+        fflush(stderr);
+    }
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
 
@@ -655,7 +808,8 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     }
     auto *m = const_cast<pcx_mlp *>(mlp);
     m->hintV.store(std::max<int64_t>(m->hintV.load(), V));
-    m->hintE.store(std::max<int64_t>(m->hintE.load(), E));
+    m->hintE.store(std::max<int64_t>(m->hintE.load(), Ebound));
+    m->hintS.store(std::max<int64_t>(m->hintS.load(), Smax));
     *out = cx;
     return PCX_OK;
 }

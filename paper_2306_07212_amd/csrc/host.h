@@ -45,7 +45,7 @@ struct pcx_mlp {
     std::vector<double *> Wt;  // device, layer l: [N_{l-1}][N_l] (transposed for coalesced GEMM reads)
     std::vector<double *> Wr;  // device, layer l: [N_l][N_{l-1}] as given (backward pass)
     std::vector<double *> b;   // device, [N_l]
-    std::atomic<int64_t> hintV{0}, hintE{0};  // sizes seen by the last extraction (capacity hint)
+    std::atomic<int64_t> hintV{0}, hintE{0}, hintS{0};  // sizes seen by earlier extractions (capacity hints)
 };
 
 struct pcx_complex {

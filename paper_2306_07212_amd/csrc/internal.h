@@ -19,8 +19,21 @@ constexpr int kGemmRows = 32;            // vertices per GEMM workgroup
 constexpr int kGemmK = 16;               // K-chunk staged in LDS
 constexpr int kMaxWidth = 256;           // widest layer the in-place GEMM handles
 
-// device counters (int32 slots of one small array)
-enum { CTR_S = 0, CTR_KVALID = 1, CTR_E = 2, CTR_FLAGS = 3, CTR_V = 4, CTR_COUNT = 8 };
+// device counters (int32 slots of one small array). The vertex and edge counts
+// and the table fill come in two slots, by the parity of the neuron step: step
+// s reads slot s & 1 and its last kernels write slot (s + 1) & 1, so no kernel
+// overwrites a count that another workgroup of the same launch still reads.
+enum {
+    CTR_S = 0,       // splitting edges of the current step (the compaction's result)
+    CTR_KVALID = 1,  // valid 2-face keys (sort pairing)
+    CTR_FLAGS = 3,   // FLAG_* bits; every per-step kernel returns at once while any is set
+    CTR_FAIL = 4,    // first step that found the storage too small (FLAG_CAPACITY)
+    CTR_SMAX = 5,    // largest split count so far in the layer (shapes the split launches)
+    CTR_V = 8,       // [2] vertex count at the start of a step
+    CTR_E = 10,      // [2] edge count at the start of a step
+    CTR_TUSED = 12,  // [2] hash-table entries a step used (cleared by the next step)
+    CTR_COUNT = 16
+};
 
 // degeneracy / failure flags (bitwise)
 enum : int {
@@ -30,6 +43,7 @@ enum : int {
     FLAG_RUN = 8,         // a 2-face key met by other than exactly two splitting edges
     FLAG_VERIFY = 16,     // equal hashes but different exact 2-face sign-vectors
     FLAG_BOUNDS = 32,     // an index outside the live arrays (internal error; the access is skipped)
+    FLAG_CAPACITY = 64,   // a step needs more storage than allocated: nothing written, the host grows and redoes it
 };
 
 // One slot of the 2-face hash table; all-zero = empty. a, b = 1 + the key
@@ -53,8 +67,17 @@ struct StepGeom {
     int zlo;         // first pre-activation column carried to new vertices: 0, or j + 1 in the
                      // last subdivided layer (no later evaluation reads the processed columns)
     int pair_mode;   // PAIR_HASH or PAIR_SORT
-    uint32_t hmask;  // hash table slots - 1 (PAIR_HASH)
+    uint32_t hmask;  // hash table slots - 1 (PAIR_HASH); the per-step kernels derive it from the split count
     HEntry *HT;      // this step's hash table (PAIR_HASH)
+    HEntry *HTo;     // the previous step's table, cleared by this step's pairing
+    int step, par;   // global neuron step and its parity (selects the CTR_V / CTR_E / CTR_TUSED slot)
+    int Vcap, Ecap, Kcap;  // storage the step may fill (else FLAG_CAPACITY)
+};
+
+// Log of one neuron step, written by its last kernel: counts at its start, its
+// split count, and the edge count after it.
+struct StepRec {
+    int V0, E0, S, E1;
 };
 
 struct Bufs {
@@ -74,27 +97,36 @@ struct Bufs {
     int *CTR;         // [CTR_COUNT]
     const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
     int2 *PQ;         // [Vcap] (V+, V-) parents of each new vertex, when the tape is recorded (else null)
+    StepRec *REC;     // [n_steps] per-step log (per-step path only; null in the batched kernel)
 };
 
 // launchers (kernels.hip)
 void launch_init_box(const Bufs &b, int D, int Wd, const double *lo, const double *hi, hipStream_t st);
 void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int relu, int V, int K, int N,
                  const double *Wt, const double *bias, int Wd, int lw0, hipStream_t st);
-void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ecap_hint, hipStream_t st);
-void launch_select(const Bufs &b, uint16_t target, hipStream_t st);
-void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st);
-// pruning during subdivision (prune.hip): kept edges -> out (count in CTR_E), their endpoints marked;
-// then marked vertices numbered in order (count in CTR_V); then rows moved and edges renumbered
-void launch_prune_edges(const Bufs &b, int V, int E, int Wd, int lwf, int2 *out, uint8_t *mark, hipStream_t st);
-void launch_prune_vertices(const Bufs &b, int V, const uint8_t *mark, int *map, hipStream_t st);
+// the edge count comes from CTR_E[par]
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ecap_hint, int par, hipStream_t st);
+// splitting edges of neuron `target` from the CTR_E[par] edges: SPL, CTR_S
+void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st);
+// V0, E0 and S come from the device counters of step g.step; `blocks` only
+// shapes the launch (the kernel strides over any S). The split also writes the
+// next step's vertex count.
+void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st);
+int split_blocks(int S_hint, int Nl);
+// pruning during subdivision (prune.hip): kept edges -> out (count in CTR_E[par]), their endpoints marked;
+// then marked vertices numbered in order (count in CTR_V[par]); then rows moved and edges renumbered
+void launch_prune_edges(const Bufs &b, int V, int E, int Wd, int lwf, int2 *out, uint8_t *mark, int par,
+                        hipStream_t st);
+void launch_prune_vertices(const Bufs &b, int V, const uint8_t *mark, int *map, int par, hipStream_t st);
 void launch_move_rows(const Bufs &b, const uint8_t *mark, const int *map, int V, int D, int Wd, int ZS, double *X2,
                       uint64_t *SG2, double *Z2, int2 *E2, int Enew, hipStream_t st);
 void launch_sort(const Bufs &b, int n, hipStream_t st);  // result in K32a/VALa
+// sort pairing (host-known counts): edges from E1 on, the edge count after the step into CTR_E[par ^ 1]
 void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st);
-// hash pairing: count + ordered emit over the key slots; the emit also clears
-// `clear_n` entries of the table used by the previous step
-void launch_hash_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, HEntry *clear_t,
-                      uint32_t clear_n, hipStream_t st);
+// hash pairing: count + ordered emit over the key slots, all counts from the
+// device; the emit also clears the previous step's table (g.HTo), writes the
+// next step's edge count and the step's log entry
+void launch_hash_pair(const Bufs &b, const StepGeom &g, hipStream_t st);
 
 // backward (backward.hip)
 template <typename T>

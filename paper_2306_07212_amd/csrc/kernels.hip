@@ -240,8 +240,8 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
 // different signs (both are nonzero there: every vertex has all of this
 // layer's entries set by the evaluation above). Edges with no such neuron
 // never split in this layer.
-__global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, int lw0, int lw1) {
-    const int E = b.CTR[CTR_E];
+__global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, int lw0, int lw1, int par) {
+    const int E = b.CTR[CTR_E + par];
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
         const int2 ab = b.EDG[e];
         if ((unsigned)ab.x >= (unsigned)V || (unsigned)ab.y >= (unsigned)V) {
@@ -257,10 +257,10 @@ __global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, in
     }
 }
 
-void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ehint, hipStream_t st) {
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ehint, int par, hipStream_t st) {
     int grid = (Ehint + kThreads - 1) / kThreads;
     grid = grid < 1 ? 1 : (grid > 8192 ? 8192 : grid);
-    hipLaunchKernelGGL(k_next_all, dim3(grid), dim3(kThreads), 0, st, b, V, Wd, lw0, lw1);
+    hipLaunchKernelGGL(k_next_all, dim3(grid), dim3(kThreads), 0, st, b, V, Wd, lw0, lw1, par);
 }
 
 // ---------------------------------------------- step 3: splitting edges
@@ -279,9 +279,10 @@ __device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
     c1 = min(E, c0 + per);
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target) {
+__global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target, int par) {
     __shared__ int s_w[kThreads / 64];
-    const int E = b.CTR[CTR_E];
+    if (b.CTR[CTR_FLAGS]) return;  // an earlier step failed: the host redoes or reports it
+    const int E = b.CTR[CTR_E + par];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int c0, c1;
     sel_chunk(E, c0, c1);
@@ -317,10 +318,11 @@ __global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target)
     if (t == 0) b.SELCNT[blockIdx.x] = run - c0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b) {
+__global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par) {
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_base;
-    const int E = b.CTR[CTR_E];
+    if (b.CTR[CTR_FLAGS]) return;
+    const int E = b.CTR[CTR_E + par];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int c0, c1;
     sel_chunk(E, c0, c1);
@@ -340,9 +342,9 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b) {
     for (int i = t; i < n; i += kThreads) b.SPL[base + i] = b.SPLX[c0 + i];
 }
 
-void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_local, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target);
-    hipLaunchKernelGGL(k_sel_gather, dim3(kSelBlocks), dim3(kThreads), 0, st, b);
+void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_local, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target, par);
+    hipLaunchKernelGGL(k_sel_gather, dim3(kSelBlocks), dim3(kThreads), 0, st, b, par);
 }
 
 // -------------------------------------------- steps 4-5a: split and keys
@@ -364,8 +366,27 @@ void launch_select(const Bufs &b, uint16_t target, hipStream_t st) {
 // ~NC+3 independent memory requests in flight per split. Lane c of chunk k
 // holds column k*G + c; the sign words of the layer come straight from the
 // chunk ballots (no LDS).
+// hash-table slots for n keys: a power of two, load factor <= 1/2
+__device__ __forceinline__ uint32_t table_size(int n) {
+    uint32_t t = 256;
+    while (t < 2u * (uint32_t)n) t <<= 1;
+    return t;
+}
+
 template <int G, int NC>
-__global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g, int V0, int E0, int S) {
+__global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
+    if (b.CTR[CTR_FLAGS]) return;
+    const int V0 = b.CTR[CTR_V + g.par], E0 = b.CTR[CTR_E + g.par], S = b.CTR[CTR_S];
+    // every later kernel of the step writes within these bounds
+    if ((int64_t)V0 + S > g.Vcap || (int64_t)E0 + (int64_t)S * g.D > g.Ecap || (int64_t)S * g.P > g.Kcap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            atomicMin(&b.CTR[CTR_FAIL], g.step);
+            atomicOr(&b.CTR[CTR_FLAGS], FLAG_CAPACITY);
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.CTR[CTR_V + (g.par ^ 1)] = V0 + S;
+    if (g.pair_mode == PAIR_HASH) g.hmask = table_size(S * g.P) - 1u;
     constexpr int groups = kThreads / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -373,21 +394,24 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g, int V
     for (int s = blockIdx.x * groups + grp; s < S; s += gridDim.x * groups) split_one<G, NC>(b, g, V0, E0, s, lane, half);
 }
 
-void launch_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S, hipStream_t st) {
-    if (S <= 0) return;
-    // two splits per wave (32-lane groups): the per-split bookkeeping on the
-    // sign words runs once for both halves of the wave
+// two splits per wave (32-lane groups): the per-split bookkeeping on the sign
+// words runs once for both halves of the wave
+int split_blocks(int S_hint, int Nl) {
+    (void)Nl;
     const int groups = kThreads / 32;
-    int grid = (S + groups - 1) / groups;
-    grid = grid > 16384 ? 16384 : grid;
+    int grid = (S_hint + groups - 1) / groups;
+    return grid < 1 ? 1 : (grid > 16384 ? 16384 : grid);
+}
+
+void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st) {
     if (g.Nl <= 32)
-        hipLaunchKernelGGL((k_split<32, 1>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 1>), dim3(blocks), dim3(kThreads), 0, st, b, g);
     else if (g.Nl <= 64)
-        hipLaunchKernelGGL((k_split<32, 2>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 2>), dim3(blocks), dim3(kThreads), 0, st, b, g);
     else if (g.Nl <= 128)
-        hipLaunchKernelGGL((k_split<32, 4>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 4>), dim3(blocks), dim3(kThreads), 0, st, b, g);
     else
-        hipLaunchKernelGGL((k_split<32, 8>), dim3(grid), dim3(kThreads), 0, st, b, g, V0, E0, S);
+        hipLaunchKernelGGL((k_split<32, 8>), dim3(blocks), dim3(kThreads), 0, st, b, g);
 }
 
 // ---------------------------------------------------- step 5b: radix sort
@@ -526,10 +550,10 @@ __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, i
         const uint32_t k = KS[i];
         // valid keys (< 2^31) sort before the sentinels: the last valid one fixes the edge count
         if (k == kSentinel) {
-            if (i == 0) b.CTR[CTR_E] = E1;
+            if (i == 0) b.CTR[CTR_E + (g.par ^ 1)] = E1;
             continue;
         }
-        if (i + 1 == nslots || KS[i + 1] == kSentinel) b.CTR[CTR_E] = E1 + (i + 1) / 2;
+        if (i + 1 == nslots || KS[i + 1] == kSentinel) b.CTR[CTR_E + (g.par ^ 1)] = E1 + (i + 1) / 2;
         if (i > 0 && KS[i - 1] == k) continue;  // not the start of a run
         int j = i + 1;
         while (j < nslots && KS[j] == k) ++j;
@@ -583,8 +607,11 @@ __device__ __forceinline__ void pair_chunk(int n, int &c0, int &c1) {
 
 // Pass 1: every key slot finds its 2-face entry once; PART[u] = the partner
 // slot if u owns the pair (the smaller slot), else -1. Per-chunk owner counts.
-__global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g, int nslots) {
+__global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g) {
     __shared__ int s_w[kThreads / 64];
+    if (b.CTR[CTR_FLAGS]) return;
+    const int S = b.CTR[CTR_S], nslots = S * g.P;
+    g.hmask = table_size(nslots) - 1u;
     int c0, c1;
     pair_chunk(nslots, c0, c1);
     int cnt = 0;
@@ -607,10 +634,14 @@ __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g, in
 
 // Pass 2: owners in slot order (chunk offsets from pass 1, ordered scatter
 // inside each chunk) append their intersecting edges.
-__global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int V0, int E1, int nslots,
-                                                          HEntry *clear_t, uint32_t clear_n) {
+__global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_base;
+    if (b.CTR[CTR_FLAGS]) return;
+    const int S = b.CTR[CTR_S], nslots = S * g.P;
+    const int V0 = b.CTR[CTR_V + g.par], E0 = b.CTR[CTR_E + g.par], E1 = E0 + S;
+    const uint32_t clear_n = (uint32_t)b.CTR[CTR_TUSED + (g.par ^ 1)];
+    HEntry *clear_t = g.HTo;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // the table of the previous step is no longer read: make it empty again
     for (uint32_t i = blockIdx.x * kThreads + t; i < clear_n; i += gridDim.x * kThreads) {
@@ -631,7 +662,14 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int
         int x = 0;
         for (int w = 0; w < kThreads / 64; ++w) x += s_w[w];
         s_base = x;
-        if (blockIdx.x == gridDim.x - 1) b.CTR[CTR_E] = E1 + x + b.SELCNT[blockIdx.x];
+        if (blockIdx.x == gridDim.x - 1) {
+            // the next step's counts, and this step's log entry
+            const int En = E1 + x + b.SELCNT[blockIdx.x];
+            b.CTR[CTR_E + (g.par ^ 1)] = En;
+            b.CTR[CTR_TUSED + g.par] = (int)table_size(nslots);
+            if (S > b.CTR[CTR_SMAX]) b.CTR[CTR_SMAX] = S;
+            if (b.REC) b.REC[g.step] = StepRec{V0, E0, S, En};
+        }
     }
     __syncthreads();
     int run = s_base;
@@ -660,11 +698,9 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g, int
     }
 }
 
-void launch_hash_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, HEntry *clear_t,
-                      uint32_t clear_n, hipStream_t st) {
-    hipLaunchKernelGGL(k_hpair_count, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g, nslots);
-    hipLaunchKernelGGL(k_hpair_emit, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g, V0, E1, nslots, clear_t,
-                       clear_n);
+void launch_hash_pair(const Bufs &b, const StepGeom &g, hipStream_t st) {
+    hipLaunchKernelGGL(k_hpair_count, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g);
+    hipLaunchKernelGGL(k_hpair_emit, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g);
 }
 
 }  // namespace pcx

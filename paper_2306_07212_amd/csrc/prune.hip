@@ -81,18 +81,19 @@ __global__ __launch_bounds__(kThreads) void k_remap_edges(int2 *E, int n, const 
 
 }  // namespace
 
-void launch_prune_edges(const Bufs &b, int V, int E, int Wd, int lwf, int2 *out, uint8_t *mark, hipStream_t st) {
+void launch_prune_edges(const Bufs &b, int V, int E, int Wd, int lwf, int2 *out, uint8_t *mark, int par,
+                        hipStream_t st) {
     EdgeKeep keep{b.EDG, b.SG, Wd, lwf, V, b.CTR};
     hipLaunchKernelGGL(k_ccount<EdgeKeep>, dim3(kChunks), dim3(kThreads), 0, st, keep, E, b.SELCNT);
     hipLaunchKernelGGL((k_cscatter<EdgeKeep, EdgeEmit>), dim3(kChunks), dim3(kThreads), 0, st, keep,
-                       EdgeEmit{b.EDG, out, mark}, E, (const int *)b.SELCNT, b.CTR + CTR_E);
+                       EdgeEmit{b.EDG, out, mark}, E, (const int *)b.SELCNT, b.CTR + CTR_E + par);
 }
 
-void launch_prune_vertices(const Bufs &b, int V, const uint8_t *mark, int *map, hipStream_t st) {
+void launch_prune_vertices(const Bufs &b, int V, const uint8_t *mark, int *map, int par, hipStream_t st) {
     Marked m{mark};
     hipLaunchKernelGGL(k_ccount<Marked>, dim3(kChunks), dim3(kThreads), 0, st, m, V, b.SELCNT);
     hipLaunchKernelGGL((k_cscatter<Marked, MapEmit>), dim3(kChunks), dim3(kThreads), 0, st, m, MapEmit{map}, V,
-                       (const int *)b.SELCNT, b.CTR + CTR_V);
+                       (const int *)b.SELCNT, b.CTR + CTR_V + par);
 }
 
 void launch_move_rows(const Bufs &b, const uint8_t *mark, const int *map, int V, int D, int Wd, int ZS, double *X2,

@@ -125,6 +125,26 @@ def test_degenerate_input_is_reported(oracle_lib, pcx):
         oracle_lib.extract(net, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
 
 
+@pytest.mark.parametrize("pairing", ["hash", "sort"])
+def test_storage_grown_by_redoing_steps(oracle_lib, pcx, monkeypatch, capfd, pairing):
+    """With hash pairing the host runs ahead of the device; the first
+    extraction of a network starts with small storage, so growing it happens
+    after a step has found it too small, wrote nothing and is redone. The
+    complex and the per-step counters are still the oracle's."""
+    import re
+    monkeypatch.setenv("PCX_VERBOSE", "1")
+    net = wl.he_mlp([3, 24, 24, 24], 77)
+    capfd.readouterr()
+    _compare(oracle_lib, pcx, net, wl.cube(3), incl=False, pairing=pairing)
+    err = capfd.readouterr().err
+    m = re.search(r"steps redone after growing the storage: (\d+)", err)
+    assert m, err[-2000:]
+    if pairing == "hash":
+        assert int(m.group(1)) > 0
+    else:
+        assert int(m.group(1)) == 0  # sort pairing sizes every step exactly
+
+
 def test_vertex_on_two_hyperplanes_is_reported(oracle_lib, pcx):
     """A new vertex that lands exactly on a later neuron's hyperplane is not
     generic either: x = 0.5 cuts the bottom edge at (0.5, -1), where the
