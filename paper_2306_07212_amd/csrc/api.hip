@@ -188,7 +188,7 @@ struct Extraction {
         // so the split list always has the edge capacity
         if (Ecap > Scap) {
             size_t c2 = Scap;
-            if ((rc = grow_keep(b.SPL, c2, Ecap, spl_used, 1))) return rc;
+            if ((rc = grow_keep(b.SPLE, c2, Ecap, spl_used, 1))) return rc;
             Scap = c2;
         }
         return PCX_OK;

@@ -86,7 +86,8 @@ struct Bufs {
     double *Z;        // [Vcap][ZS]
     int2 *EDG;        // [Ecap]
     uint16_t *NXT;    // [Ecap]
-    int *SPL;         // [Scap]
+    int *SPL;         // [Scap] split list (batched kernel)
+    int4 *SPLE;       // [Scap] split list of the per-step path: (edge, its two endpoints, 0)
     int *SPLX;        // [Ecap] per-chunk match lists of the compaction (chunk c at its own edge range)
     uint32_t *K32a, *K32b, *VALa, *VALb;  // [Kcap] radix-sort ping-pong
     uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot

@@ -338,8 +338,14 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par) {
         if (blockIdx.x == gridDim.x - 1) b.CTR[CTR_S] = x + b.SELCNT[blockIdx.x];
     }
     __syncthreads();
+    // each entry carries its edge's endpoints, so the split starts from them
+    // without another dependent load
     const int n = b.SELCNT[blockIdx.x], base = s_base;
-    for (int i = t; i < n; i += kThreads) b.SPL[base + i] = b.SPLX[c0 + i];
+    for (int i = t; i < n; i += kThreads) {
+        const int e = b.SPLX[c0 + i];
+        const int2 ab = b.EDG[e];
+        b.SPLE[base + i] = make_int4(e, ab.x, ab.y, 0);
+    }
 }
 
 void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st) {
@@ -391,7 +397,15 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     const int half = (threadIdx.x & 63) / G;
-    for (int s = blockIdx.x * groups + grp; s < S; s += gridDim.x * groups) split_one<G, NC>(b, g, V0, E0, s, lane, half);
+    for (int s = blockIdx.x * groups + grp; s < S; s += gridDim.x * groups) {
+        const int4 q = b.SPLE[s];
+        const int2 ab = make_int2(q.y, q.z);
+        if (!split_entry_ok(b, q.x, E0) || !split_edge_ok(ab, V0)) {
+            if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
+            continue;
+        }
+        split_core<G, NC>(b, g, V0, E0, s, q.x, ab, lane, half);
+    }
 }
 
 // two splits per wave (32-lane groups): the per-split bookkeeping on the sign
