@@ -181,7 +181,7 @@ struct Extraction {
         size_t c0 = Ecap, c1 = Ecap;
         int rc;
         if ((rc = grow_keep(b.EDG, c0, need, used, 1))) return rc;
-        if ((rc = grow_keep(b.NXT, c1, need, used, 1))) return rc;
+        if ((rc = grow_keep(b.NX8, c1, need, used, 1))) return rc;
         Ecap = std::min(c0, c1);
         if ((rc = grow_scratch(b.SPLX, Ecap, Ecap))) return rc;  // chunk match lists: edge capacity
         // the compaction writes up to E split ids before the host learns S,
@@ -452,7 +452,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         if ((rc = x.arena.alloc(&p, Wd * sizeof(uint64_t)))) return rc;
         x.b.VALID = (const uint64_t *)p;
         HIPCHK(hipMemcpyAsync(p, valid.data(), Wd * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-        if ((rc = x.arena.alloc(&p, (size_t)kSelBlocks * sizeof(int)))) return rc;
+        if ((rc = x.arena.alloc(&p, (size_t)kNextBlocks * sizeof(int)))) return rc;
         x.b.SELCNT = (int *)p;
     }
     double *dbox = nullptr;
@@ -555,6 +555,8 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         const int f = x.hctr[CTR_FAIL];
         if (f < 0 || f >= n_steps) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
         const int64_t Sf = x.hctr[CTR_S], Vf = x.hctr[CTR_V + (f & 1)], Ef = x.hctr[CTR_E + (f & 1)];
+        V = Vf;  // a redone first step of a layer rescans the edges from these counts
+        E = Ef;
         int r;
         // exactly what step f needs: each array that is short grows by half
         if ((r = grow_for(Vf, Ef, Sf, 1))) return r;
@@ -623,10 +625,6 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
                 if ((rc = prune_now(x, V, E, lw[l], par0))) return rc;
                 if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
             }
-            if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
-            launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, par0, st);
-            if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
-            HIPCHK(hipGetLastError());
             started = true;
             j = 0;
         }
@@ -685,8 +683,18 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         g.HTo = x.HT[par ^ 1];
         g.step = s;
         g.par = par;
-        if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-        launch_select(x.b, (uint16_t)j, par, st);
+        g.nx8 = 1;
+        if (j == 0) {
+            // the layer's first crossings; its scan is also the first pass of this step's compaction
+            if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
+            launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, par, st);
+            if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
+            if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
+            launch_gather(x.b, (int)E, par, st);
+        } else {
+            if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
+            launch_select(x.b, (uint16_t)j, par, st);
+        }
         if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
         HIPCHK(hipGetLastError());
         int64_t S = 0;

@@ -216,6 +216,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             g.HT = table;
             g.hmask = tsz - 1;
             g.zlo = 0;
+            g.nx8 = 0;
             if (P > 0) {
                 for (uint32_t i = t; i < tsz; i += kThreads) {
                     HEntry z;

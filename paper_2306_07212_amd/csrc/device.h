@@ -88,6 +88,24 @@ __device__ __forceinline__ int group_or(int v) {
     return v;
 }
 
+// bit i: edge base + i has first crossing `target` (16 one-byte entries)
+__device__ __forceinline__ uint32_t match16b(const uint8_t *__restrict__ nx, int base, int E, uint8_t target) {
+    uint32_t hit = 0;
+    if (base + kSelItems <= E) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(nx + base);
+        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (((w[i] >> (8 * k)) & 0xFFu) == target) hit |= 1u << (4 * i + k);
+    } else {
+        for (int i = 0; i < kSelItems; ++i)
+            if (base + i < E && nx[base + i] == target) hit |= 1u << i;
+    }
+    return hit;
+}
+
 __device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, int base, int E, uint16_t target) {
     uint32_t hit = 0;
     if (base + kSelItems <= E) {
@@ -192,7 +210,10 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
             if (x[i]) col = first_col(x[i], w0 + i, g.lw0);
     }
     b.EDG[out] = make_int2(xa, xb);
-    b.NXT[out] = col == kNoCol ? kNone : (uint16_t)col;
+    if (g.nx8)
+        b.NX8[out] = col == kNoCol ? 0 : (uint8_t)col;  // col > j >= 0
+    else
+        b.NXT[out] = col == kNoCol ? kNone : (uint16_t)col;
 }
 
 __device__ __forceinline__ bool hash_owner(const Bufs &b, const StepGeom &g, int u, int nslots, int &partner) {
@@ -439,8 +460,13 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         if (bad) raise_flag(b.CTR, bad);
         b.EDG[e] = make_int2(ab.x, (int)x0);
         b.EDG[E0 + s] = make_int2((int)x0, ab.y);
-        b.NXT[e] = da == kNoCol ? kNone : (uint16_t)da;
-        b.NXT[E0 + s] = db == kNoCol ? kNone : (uint16_t)db;
+        if (g.nx8) {  // crossings after j >= 0: 1..255
+            b.NX8[e] = da == kNoCol ? 0 : (uint8_t)da;
+            b.NX8[E0 + s] = db == kNoCol ? 0 : (uint8_t)db;
+        } else {
+            b.NXT[e] = da == kNoCol ? kNone : (uint16_t)da;
+            b.NXT[E0 + s] = db == kNoCol ? kNone : (uint16_t)db;
+        }
         if (b.PQ) b.PQ[x0] = apos ? ab : make_int2(ab.y, ab.x);
     }
     if (g.P > 0) {

@@ -10,6 +10,7 @@ constexpr int kThreads = 256;            // every kernel uses 256-thread workgro
 constexpr int kSelItems = 16;            // edges per thread in the compaction scan
 constexpr int kSelTile = kThreads * kSelItems;
 constexpr int kSelBlocks = 1024;         // fixed grid of the two-pass compaction
+constexpr int kNextBlocks = 8192;        // most chunks of the layer-start scan (its compaction included)
 constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile
 constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kSortBins = 256;           // 8-bit digits, 4 passes over 32-bit keys
@@ -71,6 +72,7 @@ struct StepGeom {
     HEntry *HT;      // this step's hash table (PAIR_HASH)
     HEntry *HTo;     // the previous step's table, cleared by this step's pairing
     int step, par;   // global neuron step and its parity (selects the CTR_V / CTR_E / CTR_TUSED slot)
+    int nx8;         // 1: first crossings go to NX8 (per-step path); 0: to NXT (batched kernel)
     int Vcap, Ecap, Kcap;  // storage the step may fill (else FLAG_CAPACITY)
 };
 
@@ -85,7 +87,9 @@ struct Bufs {
     uint64_t *SG;     // [Vcap][Wd]
     double *Z;        // [Vcap][ZS]
     int2 *EDG;        // [Ecap]
-    uint16_t *NXT;    // [Ecap]
+    uint16_t *NXT;    // [Ecap] first crossing in the layer, kNone if none (batched kernel)
+    uint8_t *NX8;     // [Ecap] the same on the per-step path: 1..255, 0 = none (the layer's first
+                      // neuron is never looked up: its splitting edges come from the layer-start scan)
     int *SPL;         // [Scap] split list (batched kernel)
     int4 *SPLE;       // [Scap] split list of the per-step path: (edge, its two endpoints, 0)
     int *SPLX;        // [Ecap] per-chunk match lists of the compaction (chunk c at its own edge range)
@@ -94,7 +98,7 @@ struct Bufs {
     uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus
     int *PART;        // [Kcap] hash pairing: partner slot of an owner slot, else -1
     uint32_t *HIST;   // [256 * tiles]
-    int *SELCNT;      // [kSelBlocks] per-chunk match counts of the compaction (also the pairing passes)
+    int *SELCNT;      // [kNextBlocks] per-chunk match counts of the compaction (also the pairing passes)
     int *CTR;         // [CTR_COUNT]
     const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
     int2 *PQ;         // [Vcap] (V+, V-) parents of each new vertex, when the tape is recorded (else null)
@@ -105,8 +109,12 @@ struct Bufs {
 void launch_init_box(const Bufs &b, int D, int Wd, const double *lo, const double *hi, hipStream_t st);
 void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int relu, int V, int K, int N,
                  const double *Wt, const double *bias, int Wd, int lw0, hipStream_t st);
-// the edge count comes from CTR_E[par]
-void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ecap_hint, int par, hipStream_t st);
+// first crossing of every edge in the layer (NX8; the edge count comes from
+// CTR_E[par]), and the ordered compaction of the edges that cross the layer's
+// first neuron (the first pass of that step's split list: SPLX, SELCNT)
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int par, hipStream_t st);
+// the compaction's second pass alone, after launch_next_all over the same E edges
+void launch_gather(const Bufs &b, int E, int par, hipStream_t st);
 // splitting edges of neuron `target` from the CTR_E[par] edges: SPL, CTR_S
 void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st);
 // V0, E0 and S come from the device counters of step g.step; `blocks` only

@@ -234,38 +234,9 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
                        Wd, lw0);
 }
 
-// ------------------------------------ steps 2-3 at a layer start, per edge
-//
-// For every edge, the first neuron of the layer at which its endpoints carry
-// different signs (both are nonzero there: every vertex has all of this
-// layer's entries set by the evaluation above). Edges with no such neuron
-// never split in this layer.
-__global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, int lw0, int lw1, int par) {
-    const int E = b.CTR[CTR_E + par];
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
-        const int2 ab = b.EDG[e];
-        if ((unsigned)ab.x >= (unsigned)V || (unsigned)ab.y >= (unsigned)V) {
-            raise_flag(b.CTR, FLAG_BOUNDS);
-            b.NXT[e] = kNone;
-            continue;
-        }
-        const uint64_t *ra = b.SG + (size_t)ab.x * Wd;
-        const uint64_t *rb = b.SG + (size_t)ab.y * Wd;
-        int col = kNoCol;
-        for (int w = lw0; w < lw1 && col == kNoCol; ++w) col = first_col(ra[w] ^ rb[w], w, lw0);
-        b.NXT[e] = col == kNoCol ? kNone : (uint16_t)col;
-    }
-}
-
-void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int Ehint, int par, hipStream_t st) {
-    int grid = (Ehint + kThreads - 1) / kThreads;
-    grid = grid < 1 ? 1 : (grid > 8192 ? 8192 : grid);
-    hipLaunchKernelGGL(k_next_all, dim3(grid), dim3(kThreads), 0, st, b, V, Wd, lw0, lw1, par);
-}
-
 // ---------------------------------------------- step 3: splitting edges
 //
-// Ordered stream compaction of {e : NXT[e] == target}. The edge array is cut
+// Ordered stream compaction of {e : NX8[e] == target}. The edge array is cut
 // into kSelBlocks contiguous chunks, one per workgroup. The first kernel reads
 // its chunk once and writes the matching ids in order (wave ballot / prefix sum
 // inside each tile) to the chunk's own range of SPLX, with the chunk's count;
@@ -289,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target,
     int run = c0;
     for (int tb = c0; tb < c1; tb += kSelTile) {
         const int base = tb + t * kSelItems;
-        uint32_t hit = base < c1 ? match16(b.NXT, base, c1, target) : 0u;
+        uint32_t hit = base < c1 ? match16b(b.NX8, base, c1, (uint8_t)target) : 0u;
         const int cnt = __popc(hit);
         int incl = cnt;
 #pragma unroll
@@ -351,6 +322,71 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par) {
 void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st) {
     hipLaunchKernelGGL(k_sel_local, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target, par);
     hipLaunchKernelGGL(k_sel_gather, dim3(kSelBlocks), dim3(kThreads), 0, st, b, par);
+}
+
+// ------------------------------------ steps 2-3 at a layer start, per edge
+//
+// For every edge, the first neuron of the layer at which its endpoints carry
+// different signs (both are nonzero there: every vertex has all of this
+// layer's entries set by the evaluation above). Edges with no such neuron
+// never split in this layer. Each workgroup takes one contiguous chunk of the
+// edges (one edge per thread per tile) and also writes the edges whose first
+// crossing is the layer's neuron 0, in edge order, to its chunk's range of
+// SPLX: the first pass of that step's compaction (byte 0 stands for both
+// "none" and neuron 0, which no later step looks up).
+__global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, int lw0, int lw1, int par) {
+    __shared__ int s_w[kThreads / 64];
+    if (b.CTR[CTR_FLAGS]) return;
+    const int E = b.CTR[CTR_E + par];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int c0, c1;
+    sel_chunk(E, c0, c1);
+    int run = c0;
+    for (int tb = c0; tb < c1; tb += kThreads) {
+        const int e = tb + t;
+        int col = kNoCol;
+        if (e < c1) {
+            const int2 ab = b.EDG[e];
+            if ((unsigned)ab.x >= (unsigned)V || (unsigned)ab.y >= (unsigned)V) {
+                raise_flag(b.CTR, FLAG_BOUNDS);
+            } else {
+                const uint64_t *ra = b.SG + (size_t)ab.x * Wd;
+                const uint64_t *rb = b.SG + (size_t)ab.y * Wd;
+                for (int w = lw0; w < lw1 && col == kNoCol; ++w) col = first_col(ra[w] ^ rb[w], w, lw0);
+            }
+            b.NX8[e] = (col == kNoCol || col == 0) ? 0 : (uint8_t)col;
+        }
+        const bool hit = col == 0;
+        const uint64_t m = __ballot(hit);
+        __syncthreads();  // s_w reuse
+        if (lane == 0) s_w[wave] = __popcll(m);
+        __syncthreads();
+        int wave_off = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const int ws = s_w[w];
+            if (w < wave) wave_off += ws;
+            total += ws;
+        }
+        if (hit) b.SPLX[run + wave_off + __popcll(m & below)] = e;
+        run += total;
+    }
+    if (t == 0) b.SELCNT[blockIdx.x] = run - c0;
+}
+
+// chunks of the layer-start scan: about 4096 edges each, up to kNextBlocks
+static int next_blocks(int E) {
+    int g = (E + 4095) / 4096;
+    return g < 1 ? 1 : (g > kNextBlocks ? kNextBlocks : g);
+}
+
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int par, hipStream_t st) {
+    hipLaunchKernelGGL(k_next_all, dim3(next_blocks(E)), dim3(kThreads), 0, st, b, V, Wd, lw0, lw1, par);
+}
+
+void launch_gather(const Bufs &b, int E, int par, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_gather, dim3(next_blocks(E)), dim3(kThreads), 0, st, b, par);
 }
 
 // -------------------------------------------- steps 4-5a: split and keys
