@@ -250,6 +250,7 @@ int future_signs(Extraction &x, const pcx_mlp *mlp, int l, int nsub, int64_t V, 
         const double *src = x.b.Z + (size_t)c0 * ZS;
         for (int m = l + 1; m < nsub; ++m) {
             Bufs bb = x.b;
+            bb.LW = nullptr;
             bb.Z = (double *)q[m & 1];
             bb.SG = x.b.SG + (size_t)c0 * Wd;
             launch_gemm(bb, ZS, src, ZS, 1, n, mlp->widths[m], mlp->widths[m + 1], mlp->Wt[m], mlp->b[m], Wd, lw[m],
@@ -581,6 +582,11 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
                 started = true;
                 continue;
             }
+            // the previous layer's word copies are no longer read
+            if (x.b.LW) {
+                x.arena.release(x.b.LW);
+                x.b.LW = nullptr;
+            }
             if (l == nsub) break;
             const int par0 = step0[l] & 1;
             V = x.hctr[CTR_V + par0];
@@ -600,6 +606,13 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
                         (long long)V, (long long)E, (unsigned long long)x.arena.cur,
                         (unsigned long long)x.arena.peak);
                 fflush(stderr);
+            }
+            // the evaluation also keeps the layer's sign words in 64-byte rows for the
+            // layer-start scan (not with pruning, which renumbers the vertices after it)
+            if (!x.prune) {
+                void *q;
+                if ((rc = x.arena.alloc(&q, (size_t)std::max<int64_t>(V, 1) * 8 * sizeof(uint64_t)))) return rc;
+                x.b.LW = (uint64_t *)q;
             }
             // step 1 for the whole layer: pre-activations at every vertex
             if ((rc = x.mark(PCX_K_GEMM, true))) return rc;

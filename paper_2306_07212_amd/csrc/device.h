@@ -301,8 +301,11 @@ __device__ __forceinline__ void gemm_tile(const Bufs &b, int ZS, const double *i
             }
             const uint64_t pb = __ballot(ok && z > 0.0);
             const uint64_t nb = __ballot(ok && z < 0.0);
-            if (tc == 0 && v < V && c < nwords)
-                b.SG[(size_t)v * Wd + lw0 + c] = codes_of((uint32_t)(pb >> (32 * half)), (uint32_t)(nb >> (32 * half)));
+            if (tc == 0 && v < V && c < nwords) {
+                const uint64_t cw = codes_of((uint32_t)(pb >> (32 * half)), (uint32_t)(nb >> (32 * half)));
+                b.SG[(size_t)v * Wd + lw0 + c] = cw;
+                if (b.LW) b.LW[(size_t)v * 8 + c] = cw;
+            }
         }
     }
     if (zero) raise_flag(b.CTR, FLAG_ZERO_SIGN);

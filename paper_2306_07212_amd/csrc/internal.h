@@ -103,6 +103,8 @@ struct Bufs {
     const uint64_t *VALID;  // [Wd] 01-pattern at every valid entry
     int2 *PQ;         // [Vcap] (V+, V-) parents of each new vertex, when the tape is recorded (else null)
     StepRec *REC;     // [n_steps] per-step log (per-step path only; null in the batched kernel)
+    uint64_t *LW;     // [V][8] the evaluated layer's sign words again, in 64-byte rows, for the
+                      // layer-start scan (written by the evaluation when set; else null)
 };
 
 // launchers (kernels.hip)

@@ -212,7 +212,9 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
                                          ((uint32_t)((pb[2 * p + 1] >> sh) & 0xFFFFu) << 16);
                     const uint32_t neg = (uint32_t)((nb[2 * p] >> sh) & 0xFFFFu) |
                                          ((uint32_t)((nb[2 * p + 1] >> sh) & 0xFFFFu) << 16);
-                    b.SG[(size_t)v * Wd + lw0 + word] = codes_of(pos, neg);
+                    const uint64_t cw = codes_of(pos, neg);
+                    b.SG[(size_t)v * Wd + lw0 + word] = cw;
+                    if (b.LW) b.LW[(size_t)v * 8 + word] = cw;
                 }
             }
         }
@@ -350,6 +352,24 @@ __global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, in
             const int2 ab = b.EDG[e];
             if ((unsigned)ab.x >= (unsigned)V || (unsigned)ab.y >= (unsigned)V) {
                 raise_flag(b.CTR, FLAG_BOUNDS);
+            } else if (b.LW) {
+                // the layer's words from their 64-byte copies: four aligned 16-byte loads per endpoint
+                const uint4 *ra = reinterpret_cast<const uint4 *>(b.LW + (size_t)ab.x * 8);
+                const uint4 *rb = reinterpret_cast<const uint4 *>(b.LW + (size_t)ab.y * 8);
+                uint4 qa[4], qb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    qa[i] = ra[i];
+                    qb[i] = rb[i];
+                }
+                const int nw = lw1 - lw0;
+#pragma unroll
+                for (int i = 3; i >= 0; --i) {
+                    const uint64_t x1 = (((uint64_t)(qa[i].w ^ qb[i].w)) << 32) | (qa[i].z ^ qb[i].z);
+                    const uint64_t x0 = (((uint64_t)(qa[i].y ^ qb[i].y)) << 32) | (qa[i].x ^ qb[i].x);
+                    if (2 * i + 1 < nw && x1) col = first_col(x1, lw0 + 2 * i + 1, lw0);
+                    if (2 * i < nw && x0) col = first_col(x0, lw0 + 2 * i, lw0);
+                }
             } else {
                 const uint64_t *ra = b.SG + (size_t)ab.x * Wd;
                 const uint64_t *rb = b.SG + (size_t)ab.y * Wd;
