@@ -88,19 +88,27 @@ __device__ __forceinline__ int group_or(int v) {
     return v;
 }
 
-// bit i: edge base + i has first crossing `target` (16 one-byte entries)
-__device__ __forceinline__ uint32_t match16b(const uint8_t *__restrict__ nx, int base, int E, uint8_t target) {
+// bits 0..3: which bytes of v equal the byte t4 repeats (exact: no borrow
+// between bytes, since the top bit of each byte is handled apart)
+__device__ __forceinline__ uint32_t eq_bytes4(uint32_t v, uint32_t t4) {
+    const uint32_t x = v ^ t4;
+    const uint32_t nz = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // top bit set in every nonzero byte
+    const uint32_t z = ~nz & 0x80808080u;
+    return ((z >> 7) * 0x00204081u) >> 21 & 0xFu;  // gather the four top bits
+}
+
+// bit i: edge base + i has first crossing `target` (kScanItems one-byte entries)
+__device__ __forceinline__ uint32_t match32b(const uint8_t *__restrict__ nx, int base, int E, uint8_t target) {
     uint32_t hit = 0;
-    if (base + kSelItems <= E) {
+    if (base + kScanItems <= E) {
         const uint4 a = *reinterpret_cast<const uint4 *>(nx + base);
-        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+        const uint4 c = *reinterpret_cast<const uint4 *>(nx + base + 16);
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+        const uint32_t t4 = 0x01010101u * target;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (((w[i] >> (8 * k)) & 0xFFu) == target) hit |= 1u << (4 * i + k);
+        for (int i = 0; i < 8; ++i) hit |= eq_bytes4(w[i], t4) << (4 * i);
     } else {
-        for (int i = 0; i < kSelItems; ++i)
+        for (int i = 0; i < kScanItems; ++i)
             if (base + i < E && nx[base + i] == target) hit |= 1u << i;
     }
     return hit;

@@ -9,6 +9,8 @@ namespace pcx {
 constexpr int kThreads = 256;            // every kernel uses 256-thread workgroups (4 waves)
 constexpr int kSelItems = 16;            // edges per thread in the compaction scan
 constexpr int kSelTile = kThreads * kSelItems;
+constexpr int kScanItems = 32;           // one-byte first crossings per thread in the per-step compaction
+constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kSelBlocks = 1024;         // fixed grid of the two-pass compaction
 constexpr int kNextBlocks = 8192;        // most chunks of the layer-start scan (its compaction included)
 constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile

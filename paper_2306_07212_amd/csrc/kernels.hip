@@ -247,7 +247,7 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
 // workgroup ever waits on another, so the scan runs at streaming speed on all
 // XCDs and reads each next-crossing once per step.
 __device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
-    const int per = ((E + (int)gridDim.x - 1) / (int)gridDim.x + kSelItems - 1) / kSelItems * kSelItems;
+    const int per = ((E + (int)gridDim.x - 1) / (int)gridDim.x + kScanItems - 1) / kScanItems * kScanItems;
     c0 = min(E, (int)blockIdx.x * per);
     c1 = min(E, c0 + per);
 }
@@ -260,9 +260,9 @@ __global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target,
     int c0, c1;
     sel_chunk(E, c0, c1);
     int run = c0;
-    for (int tb = c0; tb < c1; tb += kSelTile) {
-        const int base = tb + t * kSelItems;
-        uint32_t hit = base < c1 ? match16b(b.NX8, base, c1, (uint8_t)target) : 0u;
+    for (int tb = c0; tb < c1; tb += kScanTile) {
+        const int base = tb + t * kScanItems;
+        uint32_t hit = base < c1 ? match32b(b.NX8, base, c1, (uint8_t)target) : 0u;
         const int cnt = __popc(hit);
         int incl = cnt;
 #pragma unroll
