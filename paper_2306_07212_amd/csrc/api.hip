@@ -464,8 +464,28 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         HIPCHK(hipMemcpyAsync(dbox, dom.lo, D * sizeof(double), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(dbox + D, dom.hi, D * sizeof(double), hipMemcpyHostToDevice, st));
     }
-    if ((rc = x.ensure_vertices(std::max<size_t>({V0, 1024, (size_t)mlp->hintV.load()}), 0))) return rc;
-    if ((rc = x.ensure_edges(std::max<size_t>({E0, 4096, (size_t)mlp->hintE.load()}), 0, 0))) return rc;
+    // Initial storage: the sizes this network reached before, else (a first
+    // extraction) the fitted vertex predictor with half again as margin, as
+    // long as that stays small (about E = D V edges and D V / N splits per
+    // step); growth and redone steps cover the rest.
+    // (PCX_SMALL_START=1 starts from the minimum instead: a test hook for the
+    // growth path)
+    const char *small_env = getenv("PCX_SMALL_START");
+    const bool small_start = small_env && small_env[0] == '1';
+    size_t Vinit = std::max<size_t>({V0, 1024, small_start ? 0 : (size_t)mlp->hintV.load()});
+    size_t Einit = std::max<size_t>({E0, 4096, small_start ? 0 : (size_t)mlp->hintE.load()});
+    size_t Sinit = small_start ? 0 : (size_t)mlp->hintS.load();
+    if (!small_start && mlp->hintV.load() == 0 && n_steps > 0) {
+        const double pv = 1.5 * predict_vertices(D, n_steps);
+        const double per_v = 8.0 * (D + Wd + ZS) + (double)std::max(1, D) * (8 + 1 + 16 + 4);
+        if (pv * per_v <= 4.0e9) {
+            Vinit = std::max(Vinit, (size_t)pv);
+            Einit = std::max(Einit, (size_t)(pv * std::max(1, D)));
+            Sinit = std::max(Sinit, (size_t)(2.0 * pv * std::max(1, D) / n_steps) + 256);
+        }
+    }
+    if ((rc = x.ensure_vertices(Vinit, 0))) return rc;
+    if ((rc = x.ensure_edges(Einit, 0, 0))) return rc;
     {
         int h[CTR_COUNT] = {0};
         h[CTR_V] = (int)V0;
@@ -518,7 +538,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     // every step.
     const bool lagged = x.pair_mode == PAIR_HASH;
     constexpr int kAhead = 8;
-    const int64_t Shint = std::min<int64_t>(mlp->hintS.load(), (int64_t)x.Scap);
+    const int64_t Shint = std::min<int64_t>((int64_t)Sinit, (int64_t)x.Scap);
     if ((rc = x.ensure_step((size_t)Shint, (size_t)Shint * x.P))) return rc;
     x.tables_reset = false;  // new tables are zero, and so are the counters
     int64_t V = (int64_t)V0, E = (int64_t)E0;

@@ -127,12 +127,13 @@ def test_degenerate_input_is_reported(oracle_lib, pcx):
 
 @pytest.mark.parametrize("pairing", ["hash", "sort"])
 def test_storage_grown_by_redoing_steps(oracle_lib, pcx, monkeypatch, capfd, pairing):
-    """With hash pairing the host runs ahead of the device; the first
-    extraction of a network starts with small storage, so growing it happens
-    after a step has found it too small, wrote nothing and is redone. The
-    complex and the per-step counters are still the oracle's."""
+    """With hash pairing the host runs ahead of the device; starting from
+    the smallest storage, growing it happens after a step has found it too
+    small, wrote nothing and is redone. The complex and the per-step counters
+    are still the oracle's."""
     import re
     monkeypatch.setenv("PCX_VERBOSE", "1")
+    monkeypatch.setenv("PCX_SMALL_START", "1")
     net = wl.he_mlp([3, 24, 24, 24], 77)
     capfd.readouterr()
     _compare(oracle_lib, pcx, net, wl.cube(3), incl=False, pairing=pairing)
