@@ -478,7 +478,8 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     if (!small_start && mlp->hintV.load() == 0 && n_steps > 0) {
         const double pv = 1.5 * predict_vertices(D, n_steps);
         const double per_v = 8.0 * (D + Wd + ZS) + (double)std::max(1, D) * (8 + 1 + 16 + 4);
-        if (pv * per_v <= 4.0e9) {
+        // (within a quarter of a byte cap, so a cap that fits the complex is never hit by the margin)
+        if (pv * per_v <= 4.0e9 && (o.max_bytes == 0 || 4.0 * pv * per_v <= (double)o.max_bytes)) {
             Vinit = std::max(Vinit, (size_t)pv);
             Einit = std::max(Einit, (size_t)(pv * std::max(1, D)));
             Sinit = std::max(Sinit, (size_t)(2.0 * pv * std::max(1, D) / n_steps) + 256);

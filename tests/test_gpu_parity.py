@@ -146,6 +146,24 @@ def test_storage_grown_by_redoing_steps(oracle_lib, pcx, monkeypatch, capfd, pai
         assert int(m.group(1)) == 0  # sort pairing sizes every step exactly
 
 
+def test_byte_cap_that_fits_the_complex(oracle_lib, pcx):
+    """A byte cap at four times what an extraction used succeeds with the same
+    complex on a fresh network (no capacity hints), and one below it fails
+    cleanly with PCX_ERR_CAPACITY."""
+    net = wl.he_mlp([3, 20, 20, 1], 131)
+    box = wl.cube(3)
+    X, S, Ed, steps, info = gpu_complex(pcx, net, box)
+    cap = 4 * info.peak_bytes
+    X2, S2, Ed2, steps2, info2 = gpu_complex(pcx, net, box, max_bytes=cap)
+    assert info2.peak_bytes <= cap
+    assert np.array_equal(steps, steps2)
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    assert_same_complex((X2, S2, Ed2), (r.X, r.S, r.edges), coord_tol=1e-10)
+    with pytest.raises(pcx.PcxError) as e:
+        gpu_complex(pcx, net, box, max_bytes=info.peak_bytes // 8)
+    assert e.value.code == pcx.PCX_ERR_CAPACITY
+
+
 def test_vertex_on_two_hyperplanes_is_reported(oracle_lib, pcx):
     """A new vertex that lands exactly on a later neuron's hyperplane is not
     generic either: x = 0.5 cuts the bottom edge at (0.5, -1), where the
