@@ -137,8 +137,10 @@ __device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, in
 // Open addressing with linear probing on the full 64-bit key. The first
 // splitting edge to reach a 2-face claims the slot with a 64-bit CAS and
 // records its key slot in `a`; the second finds the key and records itself in
-// `b`. A third arrival means the 2-face is not met by exactly two splitting
-// edges (Sec. 4.2.2) and raises FLAG_RUN.
+// `b` (plain stores: only the key's CAS returns a value the split waits for).
+// A third arrival means the 2-face is not met by exactly two splitting edges
+// (Sec. 4.2.2): it overwrites `b`, and the slot left in neither field raises
+// FLAG_RUN when the entries are read.
 __device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H, uint32_t u, int *ctr) {
     uint32_t h = (uint32_t)H & mask;
     for (uint32_t probe = 0; probe <= mask; ++probe) {
@@ -148,7 +150,9 @@ __device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H
             return;
         }
         if (prev == (unsigned long long)H) {
-            if (atomicCAS(&T[h].b, 0u, u + 1) != 0u) raise_flag(ctr, FLAG_RUN);
+            // a plain store: a third splitting edge on this 2-face would overwrite
+            // b, and the pass that reads the entries flags the slot left in neither
+            T[h].b = u + 1;
             return;
         }
         h = (h + 1) & mask;
@@ -235,6 +239,10 @@ __device__ __forceinline__ bool hash_owner(const Bufs &b, const StepGeom &g, int
     const uint32_t a = load_u32(&g.HT[h].a), c = load_u32(&g.HT[h].b);
     if (c == 0u || a == 0u) {
         raise_flag(b.CTR, FLAG_RUN);
+        return false;
+    }
+    if (a - 1 != (uint32_t)u && c - 1 != (uint32_t)u) {
+        raise_flag(b.CTR, FLAG_RUN);  // more than two splitting edges reached this 2-face
         return false;
     }
     const uint32_t p = (a - 1 == (uint32_t)u) ? c - 1 : a - 1;
