@@ -49,7 +49,9 @@ struct EventPool {
     hipEvent_t get() {
         if (free_.empty()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // timing only: no system-scope fence, which would write back the
+            // caches between the kernels it separates
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             all_.push_back(e);
             return e;
         }
@@ -118,6 +120,17 @@ struct Extraction {
         } else {
             ev.pend.back().b = e;
         }
+        return PCX_OK;
+    }
+    // the two events of one timed launch that records them itself (its start
+    // and end, with no packets between it and its neighbours), or nulls
+    int launch_events(int fam, hipEvent_t &a, hipEvent_t &e) {
+        a = e = nullptr;
+        if (!(timing_mask & (1 << fam))) return PCX_OK;
+        a = ev.get();
+        e = ev.get();
+        if (!a || !e) return fail(PCX_ERR_DEVICE, "hipEventCreate failed");
+        ev.pend.push_back({a, e, fam});
         return PCX_OK;
     }
     int collect() {  // after a stream synchronisation
@@ -751,9 +764,9 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         g.Vcap = (int)std::min<size_t>(x.Vcap, INT32_MAX);
         g.Ecap = (int)std::min<size_t>(x.Ecap, INT32_MAX);
         g.Kcap = (int)std::min<size_t>(x.Kcap, INT32_MAX);
-        if ((rc = x.mark(PCX_K_SPLIT, true))) return rc;
-        launch_split(x.b, g, blocks, st);
-        if ((rc = x.mark(PCX_K_SPLIT, false))) return rc;
+        hipEvent_t es, ee;
+        if ((rc = x.launch_events(PCX_K_SPLIT, es, ee))) return rc;
+        launch_split(x.b, g, blocks, st, es, ee);
         HIPCHK(hipGetLastError());
         if (lagged) {
             if ((rc = x.mark(PCX_K_PAIR, true))) return rc;

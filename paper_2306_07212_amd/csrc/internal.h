@@ -124,7 +124,9 @@ void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st);
 // V0, E0 and S come from the device counters of step g.step; `blocks` only
 // shapes the launch (the kernel strides over any S). The split also writes the
 // next step's vertex count.
-void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st);
+// t0 / t1: events the launch records at the kernel's start and end (null: none)
+void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0 = nullptr,
+                  hipEvent_t t1 = nullptr);
 int split_blocks(int S_hint, int Nl);
 // pruning during subdivision (prune.hip): kept edges -> out (count in CTR_E[par]), their endpoints marked;
 // then marked vertices numbered in order (count in CTR_V[par]); then rows moved and edges renumbered

@@ -5,6 +5,7 @@
 // pre-activation evaluation (step 1) and a scan that records, per edge, the
 // first neuron of the layer whose sign differs at its endpoints (steps 2-3).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "device.h"
@@ -473,15 +474,15 @@ int split_blocks(int S_hint, int Nl) {
     return grid < 1 ? 1 : (grid > 16384 ? 16384 : grid);
 }
 
-void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st) {
+void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     if (g.Nl <= 32)
-        hipLaunchKernelGGL((k_split<32, 1>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+        hipExtLaunchKernelGGL((k_split<32, 1>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else if (g.Nl <= 64)
-        hipLaunchKernelGGL((k_split<32, 2>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+        hipExtLaunchKernelGGL((k_split<32, 2>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else if (g.Nl <= 128)
-        hipLaunchKernelGGL((k_split<32, 4>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+        hipExtLaunchKernelGGL((k_split<32, 4>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else
-        hipLaunchKernelGGL((k_split<32, 8>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+        hipExtLaunchKernelGGL((k_split<32, 8>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
 }
 
 // ---------------------------------------------------- step 5b: radix sort
