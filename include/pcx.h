@@ -154,7 +154,10 @@ int pcx_complex_device(const pcx_complex *cx, void **coords, void **signs, void 
 
 /* Kernel-family device time in milliseconds accumulated during an extraction
  * run with bit `family` of opts.timing set: family is one of the PCX_K_* values below;
- * *launches receives the number of launches timed. */
+ * *launches receives the number of launches timed. PCX_K_SPLIT launches record
+ * their own start and end events (kernel time only); the other families are
+ * timed between event markers around their launches. Each timed launch adds a
+ * few microseconds of stream time. */
 #define PCX_K_GEMM 0     /* per-layer pre-activation evaluation (step 1) */
 #define PCX_K_NEXT 1     /* per-layer first-crossing scan of every edge (steps 2-3) */
 #define PCX_K_SELECT 2   /* per-step splitting-edge compaction (step 3) */
