@@ -191,3 +191,34 @@ def test_invalid_arguments(pcx):
     with pytest.raises(pcx.PcxError) as e:
         pcx.extract(mw, np.array([-1.0, -1.0]), np.array([1.0, 1.0]))
     assert e.value.code == pcx.PCX_ERR_INVALID
+
+
+@pytest.mark.parametrize("pairing", ["hash", "sort"])
+def test_kernel_timing_leaves_the_complex_unchanged(pcx, pairing):
+    """Timed extractions (split launches record their own events, the other
+    families sit between event markers) give the same bits; every neuron
+    step's split launch is timed, and untimed families report nothing."""
+    net = wl.he_mlp([3, 24, 20, 1], 105)
+    box = wl.cube(3)
+    m = pcx.MLP.from_net(net)
+    ref = None
+    try:
+        for timing in (0, ["split"], True):
+            cx = pcx.extract(m, box.lo, box.hi, timing=timing, pairing=pairing)
+            got = cx.copy() + (cx.steps(),)
+            times = {f: cx.kernel_time(f) for f in pcx.KERNEL_FAMILIES}
+            cx.close()
+            if ref is None:
+                ref = got
+                assert all(n == 0 for _, n in times.values())
+                continue
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b)
+            ms, n = times["split"]
+            assert n >= 44 and ms > 0.0  # one launch per neuron step (redone steps add more)
+            if timing != True:  # noqa: E712
+                assert all(times[f][1] == 0 for f in pcx.KERNEL_FAMILIES if f != "split")
+            else:
+                assert times["gemm"][1] >= 2 and times["gemm"][0] > 0.0
+    finally:
+        m.close()
