@@ -46,7 +46,7 @@ def layer_table(widths, include_output=False):
 
 def algorithmic_cost(widths, steps, include_output=False):
     """Bytes (and FLOPs for the evaluation) each kernel family must move for the
-    work of one extraction; the per-unit figures are stated in the design doc."""
+    work of one extraction, from the per-step counters (per-unit figures below)."""
     D = widths[0]
     layers, Wd = layer_table(widths, include_output)
     ZS = max(x["N"] for x in layers)
