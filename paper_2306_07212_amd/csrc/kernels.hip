@@ -66,6 +66,63 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Bufs b, int ZS, const double 
     gemm_tile(b, ZS, in, in_stride, relu, V, K, N, Wt, bias, Wd, lw0, blockIdx.x * kGemmRows, hs, ws);
 }
 
+// The same evaluation for a narrow layer (N <= kGemvMaxN outputs, e.g. the
+// output neuron): one vertex per thread, its row staged through LDS in chunks
+// of kGemmK (each chunk of the workgroup's rows read in 128-byte row pieces),
+// and the same sequential fma chain over k per output as gemm_tile, so every
+// evaluation kernel rounds alike. Weights are read at uniform addresses. In
+// place as above: a thread reads its whole row before it writes it.
+constexpr int kGemvMaxN = 8;
+__global__ __launch_bounds__(kThreads) void k_gemv(Bufs b, int ZS, const double *in, int in_stride, int relu, int V,
+                                                    int K, int N, const double *__restrict__ Wt,
+                                                    const double *__restrict__ bias, int Wd, int lw0) {
+    __shared__ double hs[kThreads][kGemmK + 1];
+    const int t = threadIdx.x;
+    const int v0 = blockIdx.x * kThreads, v = v0 + t;
+    double acc[kGemvMaxN];
+#pragma unroll
+    for (int n = 0; n < kGemvMaxN; ++n) acc[n] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+        __syncthreads();  // the previous chunk has been read
+#pragma unroll
+        for (int i = 0; i < kGemmK; ++i) {
+            // element idx of the chunk: row idx / kGemmK, column idx % kGemmK
+            const int idx = t + kThreads * i, r = idx / kGemmK, k = idx % kGemmK;
+            double h = 0.0;
+            if (v0 + r < V && k0 + k < K) {
+                h = in[(size_t)(v0 + r) * in_stride + k0 + k];
+                if (relu) h = h > 0.0 ? h : 0.0;
+            }
+            hs[r][k] = h;
+        }
+        __syncthreads();
+        const int kc = min(kGemmK, K - k0);
+        for (int kk = 0; kk < kc; ++kk) {
+            const double h = hs[t][kk];
+#pragma unroll
+            for (int n = 0; n < kGemvMaxN; ++n)
+                if (n < N) acc[n] = fma(h, Wt[(size_t)(k0 + kk) * N + n], acc[n]);
+        }
+    }
+    if (v >= V) return;
+    uint32_t pos = 0, neg = 0;
+    int zero = 0;
+#pragma unroll
+    for (int n = 0; n < kGemvMaxN; ++n) {
+        if (n < N) {
+            const double z = acc[n] + bias[n];
+            b.Z[(size_t)v * ZS + n] = z;
+            zero |= (z == 0.0);
+            pos |= (uint32_t)(z > 0.0) << n;
+            neg |= (uint32_t)(z < 0.0) << n;
+        }
+    }
+    const uint64_t cw = codes_of(pos, neg);
+    b.SG[(size_t)v * Wd + lw0] = cw;
+    if (b.LW) b.LW[(size_t)v * 8] = cw;
+    if (zero) raise_flag(b.CTR, FLAG_ZERO_SIGN);
+}
+
 // The same evaluation on the matrix cores, for wide layers (N > 128, K >= 16).
 // Wave w owns columns [64 (w%4), +64) of the row band w/4 as RT x 4 tiles of
 // the FP64 16x16x4 MFMA (lane l of a tile holds rows l/16 + 4i, column l%16,
@@ -230,6 +287,11 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
         const int grid = (V + 63) / 64;
         hipLaunchKernelGGL((k_gemm_mfma<8, 2, 8, 4, false, 1>), dim3(grid), dim3(512), 0, st, b, ZS, in, in_stride, relu, V, K, N, Wt,
                            bias, Wd, lw0);
+        return;
+    }
+    if (N <= kGemvMaxN) {
+        hipLaunchKernelGGL(k_gemv, dim3((V + kThreads - 1) / kThreads), dim3(kThreads), 0, st, b, ZS, in, in_stride,
+                           relu, V, K, N, Wt, bias, Wd, lw0);
         return;
     }
     const int grid = (V + kGemmRows - 1) / kGemmRows;
