@@ -209,7 +209,8 @@ int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, cons
  * at most small_vertices vertices) are gathered into back-to-back ticks of the
  * batched kernel; whatever arrives during a tick joins the next one. Larger
  * networks run on the per-step path in large_workers threads, each on its own
- * stream, overlapping with the ticks. A result is exactly the complex
+ * stream, overlapping with the ticks; so does a small network that would be
+ * alone in its tick while a worker is free. A result is exactly the complex
  * pcx_extract returns for the same request. The server keeps the pcx_mlp
  * handle of a request until that request is released: the caller must not
  * free it before. Latency = completion - submission (host steady clock). */

@@ -7,8 +7,10 @@
 // the next tick of the batched persistent kernel: ticks run back to back, and
 // whatever arrived while one ran joins the next. Admitted large networks run on
 // the per-step path in worker threads, each on its own stream, so their kernels
-// overlap with the ticks and with each other. Every result is the complex
-// pcx_extract returns for the same request.
+// overlap with the ticks and with each other; so does a small network that
+// would be alone in its tick while a worker is free (at low load the per-step
+// path answers it sooner). Every result is the complex pcx_extract returns for
+// the same request.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -136,6 +138,11 @@ void sched_loop(pcx_server *s) {
                 Job *j = s->pending.front();
                 const bool idle = s->inflight == 0;  // always admit onto an idle GPU
                 if (!idle && s->mem_in_use + j->pred_bytes > (double)s->opts.mem_budget) break;
+                // a small request that would be alone in its tick while a worker is
+                // free: the per-step path answers it sooner than one workgroup does
+                if (j->small && tick.empty() && s->pending.size() == 1 &&
+                    s->running_large + (int)s->large_q.size() < s->opts.large_workers)
+                    j->small = false;
                 s->pending.pop_front();
                 j->t_admit = Clock::now();
                 s->mem_in_use += j->pred_bytes;

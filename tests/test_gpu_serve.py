@@ -61,12 +61,13 @@ def test_results_identical_alone_and_in_the_mix(pcx):
 
 
 def test_poisson_stream_latency_stats(pcx):
-    """Arrivals spread over time: later requests are admitted while earlier ones
-    run (several ticks), and every request completes."""
+    """Bursts of six arrivals spread over time (more than the per-step workers
+    take at once): later requests are admitted while earlier ones run (several
+    ticks), and every request completes."""
     nets = requests(60, 302)
     mlps = [pcx.MLP.from_net(n) for n in nets]
     rng = np.random.default_rng(5)
-    arrivals = np.cumsum(rng.exponential(0.004, len(nets)))
+    arrivals = np.repeat(np.cumsum(rng.exponential(0.02, len(nets) // 6)), 6)
     srv = pcx.Server()
     t0 = time.perf_counter()
     tickets = []
@@ -83,3 +84,20 @@ def test_poisson_stream_latency_stats(pcx):
     for t in tickets:
         srv.release(t)
     srv.close()
+
+
+def test_lone_small_request_runs_on_a_free_worker(pcx):
+    """A small request alone at an idle server goes to a per-step worker (a
+    tick of one workgroup would answer later); the result is the same."""
+    net = requests(1, 303)[0]
+    m = pcx.MLP.from_net(net)
+    srv = pcx.Server()
+    t = srv.submit(m, wl.cube(net.D).lo, wl.cube(net.D).hi)
+    r = srv.wait(t)
+    assert r["status"] == 0 and r["batched"] == 0
+    got = srv.copy(t)
+    for a, b in zip(got, alone(pcx, net)):
+        assert np.array_equal(a, b)
+    srv.release(t)
+    srv.close()
+    m.close()
