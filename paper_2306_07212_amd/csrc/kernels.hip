@@ -196,6 +196,7 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
     };
     auto compute = [&](int buf) {
         if (!wave_live) return;
+        __builtin_amdgcn_s_setprio(1);  // MFMA issue ahead of the other waves' staging
 #pragma unroll
         for (int kk = 0; kk < MK; kk += 4) {
             double af[RT], bf[4];
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_gemm_mfma(Bufs b, int ZS, 
                 for (int ct = 0; ct < 4; ++ct)
                     acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[rt], bf[ct], acc[rt][ct], 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
     };
 #pragma unroll
     for (int p = 0; p < PF; ++p)
