@@ -557,6 +557,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     x.tables_reset = false;  // new tables are zero, and so are the counters
     int64_t V = (int64_t)V0, E = (int64_t)E0;
     int64_t Sgrid = 64;  // split count the split launch is shaped for (any count is covered)
+    int64_t Eseen = 0;   // latest edge count the host has seen (a lower bound: shapes the compaction)
     int64_t prevE = -1, prevS = 0;  // sort pairing: the host's own step log
     bool pairs_logged = false;      //   the previous step's pair count was taken at a layer start
     const char *verbose_env = getenv("PCX_VERBOSE");
@@ -625,6 +626,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             const int par0 = step0[l] & 1;
             V = x.hctr[CTR_V + par0];
             E = x.hctr[CTR_E + par0];
+            Eseen = 0;
             // launch shape from the previous step's count until this layer's own largest is known
             const int64_t Slast = step0[l] > 0 ? x.hctr[CTR_S] : 0;
             Sgrid = Slast + Slast / 4 + 64;
@@ -696,6 +698,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
                     const int *c = x.hsnap[other];
                     x.snap_at[other] = -1;
                     Sgrid = std::max<int64_t>(Sgrid, c[CTR_SMAX] + c[CTR_SMAX] / 4 + 64);
+                    Eseen = std::max<int64_t>({Eseen, c[CTR_E], c[CTR_E + 1]});
                     if (c[CTR_FLAGS]) {
                         // stop running ahead: exact counts, then redo or report
                         if ((rc = x.drain())) return rc;
@@ -740,7 +743,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             launch_gather(x.b, (int)E, par, st);
         } else {
             if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-            launch_select(x.b, (uint16_t)j, par, st);
+            launch_select(x.b, (uint16_t)j, par, select_grid(lagged ? std::max(Eseen, E) : E), st);
         }
         if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
         HIPCHK(hipGetLastError());
@@ -770,7 +773,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         HIPCHK(hipGetLastError());
         if (lagged) {
             if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
-            launch_hash_pair(x.b, g, st);
+            launch_hash_pair(x.b, g, pair_grid(Sgrid * x.P), st);
             if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
             HIPCHK(hipGetLastError());
         } else if (S * x.P > 0) {

@@ -120,7 +120,11 @@ void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int 
 // the compaction's second pass alone, after launch_next_all over the same E edges
 void launch_gather(const Bufs &b, int E, int par, hipStream_t st);
 // splitting edges of neuron `target` from the CTR_E[par] edges: SPL, CTR_S
-void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st);
+void launch_select(const Bufs &b, uint16_t target, int par, int grid, hipStream_t st);
+// grids (<= kSelBlocks) of the per-step compaction and hash pairing for an
+// expected edge count / key-slot count: small steps take fewer workgroups
+int select_grid(int64_t edges);
+int pair_grid(int64_t slots);
 // V0, E0 and S come from the device counters of step g.step; `blocks` only
 // shapes the launch (the kernel strides over any S). The split also writes the
 // next step's vertex count.
@@ -141,7 +145,7 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, h
 // hash pairing: count + ordered emit over the key slots, all counts from the
 // device; the emit also clears the previous step's table (g.HTo), writes the
 // next step's edge count and the step's log entry
-void launch_hash_pair(const Bufs &b, const StepGeom &g, hipStream_t st);
+void launch_hash_pair(const Bufs &b, const StepGeom &g, int grid, hipStream_t st);
 
 // backward (backward.hip)
 template <typename T>

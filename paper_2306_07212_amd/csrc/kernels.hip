@@ -8,6 +8,8 @@
 #include <hip/hip_ext.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "internal.h"
 
@@ -386,9 +388,14 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par) {
     }
 }
 
-void launch_select(const Bufs &b, uint16_t target, int par, hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_local, dim3(kSelBlocks), dim3(kThreads), 0, st, b, target, par);
-    hipLaunchKernelGGL(k_sel_gather, dim3(kSelBlocks), dim3(kThreads), 0, st, b, par);
+static int clamp_grid(int64_t g) { return (int)std::min<int64_t>(kSelBlocks, std::max<int64_t>(32, g)); }
+int select_grid(int64_t edges) { return clamp_grid((edges + 2047) / 2048); }
+int pair_grid(int64_t slots) { return clamp_grid((slots + 255) / 256); }
+
+// both kernels chunk the edges by the grid they are launched with: the same one
+void launch_select(const Bufs &b, uint16_t target, int par, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_local, dim3(grid), dim3(kThreads), 0, st, b, target, par);
+    hipLaunchKernelGGL(k_sel_gather, dim3(grid), dim3(kThreads), 0, st, b, par);
 }
 
 // ------------------------------------ steps 2-3 at a layer start, per edge
@@ -833,9 +840,9 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     }
 }
 
-void launch_hash_pair(const Bufs &b, const StepGeom &g, hipStream_t st) {
-    hipLaunchKernelGGL(k_hpair_count, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g);
-    hipLaunchKernelGGL(k_hpair_emit, dim3(kSelBlocks), dim3(kThreads), 0, st, b, g);
+void launch_hash_pair(const Bufs &b, const StepGeom &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_hpair_count, dim3(grid), dim3(kThreads), 0, st, b, g);
+    hipLaunchKernelGGL(k_hpair_emit, dim3(grid), dim3(kThreads), 0, st, b, g);
 }
 
 }  // namespace pcx
