@@ -11,7 +11,7 @@ constexpr int kSelItems = 16;            // edges per thread in the compaction s
 constexpr int kSelTile = kThreads * kSelItems;
 constexpr int kScanItems = 32;           // one-byte first crossings per thread in the per-step compaction
 constexpr int kScanTile = kThreads * kScanItems;
-constexpr int kSelBlocks = 1024;         // fixed grid of the two-pass compaction
+constexpr int kSelBlocks = 1024;         // largest grid of the per-step compaction and hash pairing
 constexpr int kNextBlocks = 8192;        // most chunks of the layer-start scan (its compaction included)
 constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile
 constexpr int kSortTile = kThreads * kSortItems;

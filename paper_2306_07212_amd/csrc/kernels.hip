@@ -306,11 +306,12 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
 // ---------------------------------------------- step 3: splitting edges
 //
 // Ordered stream compaction of {e : NX8[e] == target}. The edge array is cut
-// into kSelBlocks contiguous chunks, one per workgroup. The first kernel reads
-// its chunk once and writes the matching ids in order (wave ballot / prefix sum
-// inside each tile) to the chunk's own range of SPLX, with the chunk's count;
-// the second moves each chunk's matches to its offset in SPL, the sum of the
-// counts before it (work proportional to the matches, not to the edges). No
+// into one contiguous chunk per workgroup (up to kSelBlocks; fewer for small
+// steps). The first kernel reads its chunk once and writes the matching ids in
+// order (wave ballot / prefix sum inside each tile) to the chunk's own range of
+// SPLX, with the chunk's count; the second moves each chunk's matches to their
+// offset in SPLE, the sum of the counts before it, with their endpoints (work
+// proportional to the matches, not to the edges). No
 // workgroup ever waits on another, so the scan runs at streaming speed on all
 // XCDs and reads each next-crossing once per step.
 __device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
