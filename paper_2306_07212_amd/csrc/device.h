@@ -132,7 +132,7 @@ __device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, in
     return hit;
 }
 
-// ----------------------------------------------- 2-face hash table (f1)
+// ----------------------------------------------- 2-face hash table
 //
 // Open addressing with linear probing on the full 64-bit key. The first
 // splitting edge to reach a 2-face claims the slot with a 64-bit CAS and
@@ -161,9 +161,10 @@ __device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H
 }
 
 // Table words are read with workgroup-scope atomic loads, which skip the L1:
-// inside the persistent batched kernel the entries were last written by
-// atomics of other waves of the same workgroup (one CU, one L2); across the
-// per-step kernels a launch boundary already orders them.
+// inside the persistent batched kernel the entries were last written (CAS on
+// the key, plain store of `b`) by other waves of the same workgroup, before
+// the barrier that ends the split phase (one CU: the writes are in its L2);
+// across the per-step kernels a launch boundary already orders them.
 __device__ __forceinline__ unsigned long long load_key(const HEntry *T, uint32_t h) {
     return __hip_atomic_load(&T[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }

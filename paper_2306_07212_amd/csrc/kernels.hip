@@ -499,8 +499,9 @@ void launch_gather(const Bufs &b, int E, int par, hipStream_t st) {
 // Every load of a split (both endpoint rows of pre-activations, signs and
 // coordinates) is issued before any arithmetic or store, so a wave keeps
 // ~NC+3 independent memory requests in flight per split. Lane c of chunk k
-// holds column k*G + c; the sign words of the layer come straight from the
-// chunk ballots (no LDS).
+// holds column k*G + c; the sign words of the layer are built from the chunk
+// ballots, parked in LDS for the lane that owns each word.
+
 // hash-table slots for n keys: a power of two, load factor <= 1/2
 __device__ __forceinline__ uint32_t table_size(int n) {
     uint32_t t = 256;
@@ -737,7 +738,7 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, h
     hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kThreads), 0, st, b, g, V0, E1, nslots);
 }
 
-// ---------------------------------- step 5c with the hash table (f1)
+// ---------------------------------- step 5c with the hash table
 //
 // Every valid key slot u finds its 2-face entry; the smaller of the two slots
 // owns the pair. Owners are emitted in slot order (chunk counts, then an
