@@ -206,6 +206,81 @@ def form_batched(args, pcx, wl, torch):
             "speedup_vs_plain": (st.total_splits / T) / plain_rate}
 
 
+def form_configs(args, pcx, wl, torch):
+    """The small configurations against the CPU oracle (one core): the
+    2-8-8-1 and the 3-64-64-64-1 (with its output) networks whole, the 4096
+    batched networks on a stratified sample; the GPU side as the library runs
+    each (per-step path, batched kernel). The 768-neuron network is the plain
+    bench line."""
+    import oracle
+    oracle.build(force=False)
+
+    def gpu_single(net, incl):
+        m = pcx.MLP.from_net(net)
+        box = wl.cube(net.D)
+        for _ in range(max(1, args.warmup)):
+            pcx.extract(m, box.lo, box.hi, include_output=incl).close()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(1, args.steps)):
+            t = time.perf_counter()
+            cx = pcx.extract(m, box.lo, box.hi, include_output=incl)
+            info = cx.info()
+            cx.close()
+            ts.append(time.perf_counter() - t)
+        m.close()
+        return float(np.median(ts)), info
+
+    rows = {}
+    for key, name, incl in (("C1", "plain_small", False), ("C5", "differentiable", True)):
+        net = getattr(wl, name)()
+        box = wl.cube(net.D)
+        T, info = gpu_single(net, incl)
+        t = time.perf_counter()
+        r = oracle.extract(net, box.lo, box.hi, include_output=incl)
+        To = time.perf_counter() - t
+        splits = int(r.steps[:, 2].sum())
+        assert (r.V, r.E) == (info.V, info.E)
+        rows[key] = {"network": "-".join(map(str, net.widths)), "V": info.V, "E": info.E, "splits": splits,
+                     "gpu_ms": T * 1e3, "oracle_1core_ms": To * 1e3, "speedup": To / T,
+                     "gpu_edges_subdivided_per_s": splits / T}
+    # C3: the batched kernel on all 4096 networks; the oracle on every 64th one
+    nets = wl.batch_nets()
+    box = wl.cube(2)
+    mlps = [pcx.MLP.from_net(n) for n in nets]
+    boxes = [(box.lo, box.hi)] * len(nets)
+    for _ in range(max(1, args.warmup)):
+        pcx.Batch(mlps, boxes).close()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(1, args.steps)):
+        t = time.perf_counter()
+        bt = pcx.Batch(mlps, boxes)
+        st = bt.stats()
+        bt.close()
+        ts.append(time.perf_counter() - t)
+    for m in mlps:
+        m.close()
+    T = float(np.median(ts))
+    sample = range(0, len(nets), 64)
+    t = time.perf_counter()
+    o_splits = 0
+    for i in sample:
+        o_splits += int(oracle.extract(nets[i], box.lo, box.hi).steps[:, 2].sum())
+    To = time.perf_counter() - t
+    gpu_rate, o_rate = st.total_splits / T, o_splits / To
+    rows["C3"] = {"network": "4096 x 2-[w]xd-1", "V": st.total_V, "E": st.total_E, "splits": st.total_splits,
+                  "gpu_ms": T * 1e3, "gpu_edges_subdivided_per_s": gpu_rate,
+                  "oracle_1core_edges_subdivided_per_s": o_rate, "oracle_sample": f"{len(sample)} of 4096 networks "
+                  f"({o_splits} splits in {To:.2f} s)", "speedup": gpu_rate / o_rate}
+    return {"metric": METRIC, "value": rows["C5"]["gpu_edges_subdivided_per_s"], "unit": "edges subdivided/s (C5)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rows["C5"]["gpu_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "small configurations against the CPU oracle (one core): 2-8-8-1, "
+                                   "3-64-64-64-1 with its output, 4096 batched networks", "parallelism": "single GPU"},
+            "configs": rows}
+
+
 def form_served(args, pcx, wl, torch):
     """Poisson stream of 2000 requests (D in {2,3}, widths 16-128, depths 2-4):
     continuous batching vs the per-step path as a FIFO single server."""
@@ -414,7 +489,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain_large", help="workloads function name (default: the 768-neuron net)")
     ap.add_argument("--pairing", default="hash", choices=["hash", "sort"], help="step-5 grouping of 2-face keys")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "backward", "levelset", "simplex"],
+    ap.add_argument("--form", default="plain",
+                    choices=["plain", "batched", "served", "backward", "levelset", "simplex", "configs"],
                     help="plain (default): one large network; the others measure the systems forms")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one 1 GiB device copy (reads 1 GiB, writes 1 GiB): the reference for "
@@ -446,7 +522,7 @@ def main():
         del a, b
     if args.form != "plain":
         fn = {"batched": form_batched, "served": form_served, "backward": form_backward,
-              "levelset": form_levelset, "simplex": form_simplex}[args.form]
+              "levelset": form_levelset, "simplex": form_simplex, "configs": form_configs}[args.form]
         print(json.dumps(fn(args, pcx, wl, torch)), flush=True)
         return
 
