@@ -778,11 +778,12 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             HIPCHK(hipGetLastError());
         } else if (S * x.P > 0) {
             if ((rc = x.mark(PCX_K_SORT, true))) return rc;
-            launch_sort(x.b, (int)(S * x.P), st);
+            const uint32_t *skeys = nullptr, *svals = nullptr;
+            launch_sort(x.b, (int)(S * x.P), st, &skeys, &svals);
             if ((rc = x.mark(PCX_K_SORT, false))) return rc;
             HIPCHK(hipGetLastError());
             if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
-            launch_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), st);
+            launch_pair(x.b, g, (int)V, (int)(E + S), (int)(S * x.P), skeys, svals, st);
             if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
             HIPCHK(hipGetLastError());
         } else {

@@ -15,8 +15,9 @@ constexpr int kSelBlocks = 1024;         // largest grid of the per-step compact
 constexpr int kNextBlocks = 8192;        // most chunks of the layer-start scan (its compaction included)
 constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile
 constexpr int kSortTile = kThreads * kSortItems;
-constexpr int kSortBins = 256;           // 8-bit digits, 4 passes over 32-bit keys
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // key of an unused 2-face slot (valid keys < 2^31)
+constexpr int kSortBins = 256;           // 8-bit digits
+constexpr int kSortPasses = 3;           // over the low 24 key bits: valid keys < 2^23, the sentinel's all set
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // key of an unused 2-face slot (valid keys < 2^23)
 constexpr uint16_t kNone = 0xFFFF;       // "no further crossing in this layer"
 constexpr int kGemmRows = 32;            // vertices per GEMM workgroup
 constexpr int kGemmK = 16;               // K-chunk staged in LDS
@@ -139,9 +140,11 @@ void launch_prune_edges(const Bufs &b, int V, int E, int Wd, int lwf, int2 *out,
 void launch_prune_vertices(const Bufs &b, int V, const uint8_t *mark, int *map, int par, hipStream_t st);
 void launch_move_rows(const Bufs &b, const uint8_t *mark, const int *map, int V, int D, int Wd, int ZS, double *X2,
                       uint64_t *SG2, double *Z2, int2 *E2, int Enew, hipStream_t st);
-void launch_sort(const Bufs &b, int n, hipStream_t st);  // result in K32a/VALa
+// result: *keys / *vals (K32a/VALa or K32b/VALb, by the pass count)
+void launch_sort(const Bufs &b, int n, hipStream_t st, const uint32_t **keys, const uint32_t **vals);
 // sort pairing (host-known counts): edges from E1 on, the edge count after the step into CTR_E[par ^ 1]
-void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st);
+void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, const uint32_t *keys,
+                 const uint32_t *vals, hipStream_t st);
 // hash pairing: count + ordered emit over the key slots, all counts from the
 // device; the emit also clears the previous step's table (g.HTo), writes the
 // next step's edge count and the step's log entry

@@ -560,9 +560,12 @@ void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, 
 
 // ---------------------------------------------------- step 5b: radix sort
 //
-// Stable LSD radix sort of (32-bit key, slot) pairs, 8-bit digits, 4 passes.
-// Per pass: tile histograms, one exclusive scan over [digit][tile], and a
-// stable scatter that ranks equal digits inside a tile by wave ballots.
+// Stable LSD radix sort of (key, slot) pairs, 8-bit digits, kSortPasses passes
+// over the low 24 bits (keys are 23-bit slices of the 2-face hash; the sentinel
+// of an unused slot sorts last).
+// Per pass: tile histograms, an exclusive scan over the tiles of each digit
+// (one workgroup per digit), and a stable scatter that adds the totals of the
+// smaller digits and ranks equal digits inside a tile by wave ballots.
 __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *__restrict__ keys, int n, int shift,
                                                          uint32_t *__restrict__ hist, int ntiles) {
     __shared__ uint32_t h[kSortBins];
@@ -578,17 +581,19 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *__restri
     hist[(size_t)t * ntiles + tile] = h[t];
 }
 
-// exclusive scan of the [digit][tile] histogram in place: one workgroup of
-// 1024 threads, 4 consecutive counters per thread, coalesced 16-byte accesses
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, int len) {
-    __shared__ uint32_t wsum[16];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+// per digit d (one workgroup each): exclusive scan of hist[d][0..ntiles) in
+// place, and the digit's total in hist[kSortBins * ntiles + d] (the scatter
+// adds the totals of the smaller digits itself)
+__global__ __launch_bounds__(kThreads) void k_sort_scan(uint32_t *hist, int ntiles) {
+    __shared__ uint32_t wsum[kThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, d = blockIdx.x;
+    uint32_t *h = hist + (size_t)d * ntiles;
     uint32_t carry = 0;
-    for (int base = 0; base < len; base += 4096) {
+    for (int base = 0; base < ntiles; base += 4 * kThreads) {
         const int i0 = base + 4 * t;
         uint32_t x[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = i0 + k < len ? hist[i0 + k] : 0u;
+        for (int k = 0; k < 4; ++k) x[k] = i0 + k < ntiles ? h[i0 + k] : 0u;
         const uint32_t tsum = x[0] + x[1] + x[2] + x[3];
         uint32_t incl = tsum;
 #pragma unroll
@@ -600,7 +605,7 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, int len) {
         __syncthreads();
         uint32_t woff = 0, total = 0;
 #pragma unroll
-        for (int w = 0; w < 16; ++w) {
+        for (int w = 0; w < kThreads / 64; ++w) {
             const uint32_t v = wsum[w];
             if (w < wave) woff += v;
             total += v;
@@ -608,12 +613,13 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, int len) {
         uint32_t run = carry + woff + incl - tsum;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (i0 + k < len) hist[i0 + k] = run;
+            if (i0 + k < ntiles) h[i0 + k] = run;
             run += x[k];
         }
         carry += total;
         __syncthreads();
     }
+    if (t == 0) hist[(size_t)kSortBins * ntiles + d] = carry;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t *__restrict__ kin,
@@ -624,7 +630,23 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t *__res
     __shared__ uint32_t base[kSortBins];
     __shared__ uint32_t wcnt[kThreads / 64][kSortBins];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, tile = blockIdx.x;
-    base[t] = hist[(size_t)t * ntiles + tile];
+    static_assert(kSortBins == kThreads, "one digit per thread");
+    // digit t starts after the keys of all smaller digits: exclusive scan of the totals
+    const uint32_t tot = hist[(size_t)kSortBins * ntiles + t];
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wcnt[0][wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w)
+        if (w < wave) woff += wcnt[0][w];
+    base[t] = woff + incl - tot + hist[(size_t)t * ntiles + tile];
+    __syncthreads();  // wcnt[0] read by every wave before it is cleared
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) wcnt[w][t] = 0;
     __syncthreads();
@@ -662,20 +684,20 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t *__res
     }
 }
 
-void launch_sort(const Bufs &b, int n, hipStream_t st) {
-    if (n <= 0) return;
-    const int ntiles = (n + kSortTile - 1) / kSortTile;
+void launch_sort(const Bufs &b, int n, hipStream_t st, const uint32_t **keys, const uint32_t **vals) {
     uint32_t *ka = b.K32a, *kb = b.K32b, *va = b.VALa, *vb = b.VALb;
-    for (int pass = 0; pass < 4; ++pass) {
+    const int ntiles = (n + kSortTile - 1) / kSortTile;
+    for (int pass = 0; n > 0 && pass < kSortPasses; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(kThreads), 0, st, ka, n, shift, b.HIST, ntiles);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, b.HIST, kSortBins * ntiles);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kThreads), 0, st, b.HIST, ntiles);
         hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(kThreads), 0, st, ka, pass == 0 ? nullptr : va, kb, vb,
                            n, shift, b.HIST, ntiles);
         uint32_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
-    // four passes: the result is back in K32a / VALa
+    *keys = ka;
+    *vals = va;
 }
 
 // ------------------------------------------- step 5c: pair and connect
@@ -683,16 +705,15 @@ void launch_sort(const Bufs &b, int n, hipStream_t st) {
 // In the sorted key array every run of equal keys has even length (each
 // splitting 2-face is met by exactly two splitting edges, Sec. 4.2.2), so the
 // run starting at sorted position i owns output edges i/2, i/2+1, ... A run of
-// two is the common case; a longer run (two faces whose 31-bit keys collide)
+// two is the common case; a longer run (two faces whose 23-bit keys collide)
 // is grouped by the full 64-bit hash. Every pair is verified by comparing the
 // two perturbed sign-vectors word by word. The new edge joins the two new
 // vertices; its sign is the face's with 0 at the current neuron (Sec. 4.2.2).
-__global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, int E1, int nslots) {
-    const uint32_t *KS = b.K32a;
-    const uint32_t *VS = b.VALa;
+__global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, int E1, int nslots,
+                                                    const uint32_t *__restrict__ KS, const uint32_t *__restrict__ VS) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += gridDim.x * blockDim.x) {
         const uint32_t k = KS[i];
-        // valid keys (< 2^31) sort before the sentinels: the last valid one fixes the edge count
+        // valid keys (< 2^23) sort before the sentinels: the last valid one fixes the edge count
         if (k == kSentinel) {
             if (i == 0) b.CTR[CTR_E + (g.par ^ 1)] = E1;
             continue;
@@ -732,10 +753,11 @@ __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, i
     }
 }
 
-void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, hipStream_t st) {
+void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, const uint32_t *keys,
+                 const uint32_t *vals, hipStream_t st) {
     int grid = (nslots + kThreads - 1) / kThreads;
     grid = grid < 1 ? 1 : (grid > 8192 ? 8192 : grid);
-    hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kThreads), 0, st, b, g, V0, E1, nslots);
+    hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kThreads), 0, st, b, g, V0, E1, nslots, keys, vals);
 }
 
 // ---------------------------------- step 5c with the hash table
