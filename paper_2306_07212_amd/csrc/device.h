@@ -501,7 +501,9 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
             const size_t slot = sbase + lane;
             b.PINFO[slot] = ((uint32_t)kw << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
             if (g.pair_mode == PAIR_SORT) {
-                b.K32a[slot] = (uint32_t)(myh >> 41);  // 23 bits: three 8-bit radix passes
+                // 24 bits for three 8-bit radix passes; all-ones is the sentinel's
+                const uint32_t k24 = (uint32_t)(myh >> 40);
+                b.K32a[slot] = k24 < 0xFFFFFFu ? k24 : 0xFFFFFEu;
                 b.FULL[slot] = myh;
             } else {
                 const uint64_t hk = myh | (1ull << 63);  // never 0 (= empty)

@@ -16,8 +16,8 @@ constexpr int kNextBlocks = 8192;        // most chunks of the layer-start scan 
 constexpr int kSortItems = 8;            // keys per thread in a radix-sort tile
 constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kSortBins = 256;           // 8-bit digits
-constexpr int kSortPasses = 3;           // over the low 24 key bits: valid keys < 2^23, the sentinel's all set
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // key of an unused 2-face slot (valid keys < 2^23)
+constexpr int kSortPasses = 3;           // over the low 24 key bits: valid keys < 2^24 - 1, the sentinel's all set
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // key of an unused 2-face slot (valid keys < 2^24 - 1)
 constexpr uint16_t kNone = 0xFFFF;       // "no further crossing in this layer"
 constexpr int kGemmRows = 32;            // vertices per GEMM workgroup
 constexpr int kGemmK = 16;               // K-chunk staged in LDS

@@ -561,8 +561,8 @@ void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, 
 // ---------------------------------------------------- step 5b: radix sort
 //
 // Stable LSD radix sort of (key, slot) pairs, 8-bit digits, kSortPasses passes
-// over the low 24 bits (keys are 23-bit slices of the 2-face hash; the sentinel
-// of an unused slot sorts last).
+// over the low 24 bits (keys are 24-bit slices of the 2-face hash, all-ones
+// excluded; the sentinel of an unused slot sorts last).
 // Per pass: tile histograms, an exclusive scan over the tiles of each digit
 // (one workgroup per digit), and a stable scatter that adds the totals of the
 // smaller digits and ranks equal digits inside a tile by wave ballots.
@@ -705,7 +705,7 @@ void launch_sort(const Bufs &b, int n, hipStream_t st, const uint32_t **keys, co
 // In the sorted key array every run of equal keys has even length (each
 // splitting 2-face is met by exactly two splitting edges, Sec. 4.2.2), so the
 // run starting at sorted position i owns output edges i/2, i/2+1, ... A run of
-// two is the common case; a longer run (two faces whose 23-bit keys collide)
+// two is the common case; a longer run (two faces whose 24-bit keys collide)
 // is grouped by the full 64-bit hash. Every pair is verified by comparing the
 // two perturbed sign-vectors word by word. The new edge joins the two new
 // vertices; its sign is the face's with 0 at the current neuron (Sec. 4.2.2).
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, i
                                                     const uint32_t *__restrict__ KS, const uint32_t *__restrict__ VS) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += gridDim.x * blockDim.x) {
         const uint32_t k = KS[i];
-        // valid keys (< 2^23) sort before the sentinels: the last valid one fixes the edge count
+        // valid keys (< 2^24 - 1) sort before the sentinels: the last valid one fixes the edge count
         if (k == kSentinel) {
             if (i == 0) b.CTR[CTR_E + (g.par ^ 1)] = E1;
             continue;
