@@ -81,6 +81,50 @@ def algorithmic_cost(widths, steps, include_output=False):
     return by, flops
 
 
+def survey_bytes(widths, steps, include_output=False):
+    """Algorithmic bytes of the subdivision steps as the scope table counts them
+    (per neuron step n: z column, sign write, edge endpoints, two 2-bit endpoint
+    lookups, the split's read of two rows and write of one (coordinates, the
+    pre-activations of the neurons after n in its layer, sign words) plus two
+    edges, 2-face key write + read, new edges):
+
+        B_n = 8 V_n + V_n/4 + 8 E_n + E_n/2 + S_n [3 (8D + 8 L_n + 8 Wd) + 12] + 24 K_n + 4 K_n
+
+    with L_n = neurons after n in its layer. Returns (sum of B_n, the split's
+    share: S_n [3 (8D + 8 L_n + 8 Wd) + 12] + 12 K_n)."""
+    D = widths[0]
+    layers, Wd = layer_table(widths, include_output)
+    total = split = 0.0
+    s0 = 0
+    for ly in layers:
+        N = ly["N"]
+        for j, st in enumerate(steps[s0:s0 + N]):
+            V, E, S, K = (float(v) for v in st)
+            Ln = N - j - 1
+            sp = S * (3 * (8.0 * D + 8.0 * Ln + 8.0 * Wd) + 12) + 12.0 * K
+            split += sp
+            total += 8 * V + V / 4 + 8 * E + E / 2 + sp + 12.0 * K + 4.0 * K
+        s0 += N
+    return total, split
+
+
+def host_cpu():
+    """CPU model and hardware threads of the host the CPU baseline runs on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["kernels.hip", "device.h", "internal.h"]
 # kernel name prefix -> family (the per-step path's kernels)
@@ -159,7 +203,8 @@ def cpu_baseline(net, half=0.08):
     splits = int(r.steps[:, 2].sum())
     return {"value": splits / dt, "unit": "edges subdivided/s", "cores": 1, "kind": "oracle",
             "sample": f"same 3-256-256-256-1 network on the centred sub-box [-{half},{half}]^3 "
-                      f"(all 768 neurons): {r.V} vertices, {r.E} edges, {splits} splits in {dt:.1f} s"}
+                      f"(all 768 neurons): {r.V} vertices, {r.E} edges, {splits} splits in {dt:.1f} s "
+                      "(the oracle is single-threaded)", **host_cpu()}
 
 
 def pct(v, q):
@@ -574,28 +619,56 @@ def main():
     cx.copy()
     cx.close()
     T_d2h = time.perf_counter() - t1
+    # outside the timed region: every family timed in each of R extractions (per-family medians)
+    R = 10
+    runs = []
+    for _ in range(R):
+        cx = run(True)
+        runs.append({f: cx.kernel_time(f) for f in FAMILIES})
+        cx.close()
+    med_ms = {f: float(np.median([r[f][0] for r in runs])) for f in FAMILIES}
+    med_launch_s = {f: float(np.median([r[f][0] / 1e3 / max(1, r[f][1]) for r in runs])) for f in FAMILIES}
 
     by, flops = algorithmic_cost(net.widths, steps, incl)
+    b8_total, b8_split = survey_bytes(net.widths, steps, incl)
     avg_launch_s = dom_ms / 1e3 / max(1, dom_launches)
     per_ext_launches = dom_launches
     if dom == "gemm":
         achieved = flops / per_ext_launches / avg_launch_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS}
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS,
+                "flop_per_launch": flops / per_ext_launches}
     else:
-        achieved = by[dom] / per_ext_launches / avg_launch_s / 1e9
+        # the scope table's count: for the split, L_n = neurons after n in its layer
+        per_launch = (b8_split if dom == "split" else by[dom]) / per_ext_launches
+        achieved = per_launch / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS}
-    # every family, from the warm-up's per-family event times (all families timed at once)
+                "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": per_launch,
+                "bytes_rule": "scope-table count: S_n [3 (8D + 8 L_n + 8 Wd) + 12] + 12 K_n per step"
+                if dom == "split" else "per-unit figures of the kernel family"}
+        roof["frac_median_of_runs"] = per_launch / med_launch_s[dom] / 1e9 / HBM_PEAK_GBS
+        if dom == "split":
+            # the same launches counted with every carried pre-activation column the split moves
+            # (all N of the layer except in the last subdivided layer: the next evaluation reads them)
+            cpl = by["split"] / per_ext_launches
+            roof["carried_columns"] = {"bytes_per_launch": cpl, "achieved": cpl / avg_launch_s / 1e9,
+                                       "frac": cpl / avg_launch_s / 1e9 / HBM_PEAK_GBS}
+    # every family, from the per-family medians of the R extractions with all families timed
     fam_roof = {}
     for f in FAMILIES:
-        if fam_ms[f] <= 0:
+        if med_ms[f] <= 0:
             continue
-        s = fam_ms[f] / 1e3
-        fam_roof[f] = {"ms": fam_ms[f], "GB_per_s": by[f] / s / 1e9, "hbm_frac": by[f] / s / 1e9 / HBM_PEAK_GBS}
+        s_ = med_ms[f] / 1e3
+        fam_roof[f] = {"ms": med_ms[f], "GB_per_s": by[f] / s_ / 1e9, "hbm_frac": by[f] / s_ / 1e9 / HBM_PEAK_GBS,
+                       "avg_launch_us": med_launch_s[f] * 1e6}
         if f == "gemm":
-            fam_roof[f]["TFLOP_per_s"] = flops / s / 1e12
-            fam_roof[f]["alu_frac"] = flops / s / 1e12 / FP64_PEAK_TFLOPS
+            fam_roof[f]["TFLOP_per_s"] = flops / s_ / 1e12
+            fam_roof[f]["mfma_frac"] = flops / s_ / 1e12 / FP64_PEAK_TFLOPS
+    sub_ms = sum(med_ms[f] for f in ("next", "select", "split", "sort", "pair"))
+    subdivision = {"bytes": b8_total, "ms": sub_ms, "GB_per_s": b8_total / (sub_ms / 1e3) / 1e9,
+                   "hbm_frac": b8_total / (sub_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                   "kernels": "first-crossing scan, compaction, split, pairing (steps 2-5), medians of "
+                              f"{R} extractions"}
     roof["traffic"] = traffic_record(dom)
     roof["kernel"] = dom
     roof["launches_per_step"] = per_ext_launches
@@ -627,6 +700,7 @@ def main():
         "device_ms_per_step": info.time_ms,
         "kernel_ms_warmup": fam_ms,
         "roofline": roof,
+        "subdivision": subdivision,
         "families": fam_roof,
     }
     if not args.no_cpu_baseline:

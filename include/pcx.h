@@ -51,7 +51,7 @@ extern "C" {
 #define PCX_ERR_CAPACITY (-5)   /* result would exceed pcx_opts.max_bytes */
 
 #define PCX_PAIR_HASH 0 /* open-addressing table on 64-bit 2-face hashes, linear time */
-#define PCX_PAIR_SORT 1 /* LSD radix sort of 31-bit 2-face keys (the paper's sort, Sec. 5.1) */
+#define PCX_PAIR_SORT 1 /* LSD radix sort of 24-bit slices of the 2-face keys (the paper's sort, Sec. 5.1) */
 
 typedef struct pcx_mlp pcx_mlp;
 typedef struct pcx_complex pcx_complex;
@@ -227,6 +227,8 @@ typedef struct {
     int32_t batched;        /* 1: ran in a batched tick, 0: on the per-step path */
     int64_t V, E, total_splits;
     double latency_ms, queue_ms;  /* submission to completion / to admission */
+    int32_t D, Wd;          /* row sizes of the result: pcx_server_copy writes V*D doubles,
+                               V*Wd sign words (output word included with include_output), E*2 ints */
 } pcx_server_result;
 typedef struct {
     int64_t completed;

@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc, FP64, no FMA contraction."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -58,6 +58,8 @@ def _load():
     lib.pcxo_extract_simplex.restype = vp
     lib.pcxo_extract_simplex.argtypes = [C.POINTER(_Net), C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int]
     lib.pcxo_free.argtypes = [vp]
+    lib.pcxo_set_threads.argtypes = [C.c_int]
+    lib.pcxo_set_threads.restype = None
     for name, rt in [("pcxo_status", C.c_int), ("pcxo_V", C.c_long), ("pcxo_E", C.c_long),
                      ("pcxo_M", C.c_int), ("pcxo_n_steps", C.c_int), ("pcxo_min_margin", C.c_double)]:
         getattr(lib, name).restype = rt
@@ -115,15 +117,22 @@ class OracleResult:
         return self.edges.shape[0]
 
 
-def extract(net, lo, hi, include_output: bool = False, mutation: int = 0, prune: bool = False) -> OracleResult:
-    """Edge subdivision of ``net`` on the box [lo, hi] (float64, single thread).
-    ``prune`` (with ``include_output``): drop, before each layer, the edges whose
-    vertices agree on every neuron still to come (Sec. 5.4.2)."""
+def extract(net, lo, hi, include_output: bool = False, mutation: int = 0, prune: bool = False,
+            threads: int = 1) -> OracleResult:
+    """Edge subdivision of ``net`` on the box [lo, hi] (float64; the per-vertex
+    loops on ``threads`` threads, one by default: the result does not depend on
+    it). ``prune`` (with ``include_output``): drop, before each layer, the edges
+    whose vertices agree on every neuron still to come (Sec. 5.4.2)."""
     lib = _load()
     h = _NetHolder(net.widths, net.W, net.b)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
-    r = lib.pcxo_extract(C.byref(h.c), _dp(lo), _dp(hi), int(bool(include_output)), int(bool(prune)), int(mutation))
+    lib.pcxo_set_threads(int(threads))
+    try:
+        r = lib.pcxo_extract(C.byref(h.c), _dp(lo), _dp(hi), int(bool(include_output)), int(bool(prune)),
+                             int(mutation))
+    finally:
+        lib.pcxo_set_threads(1)
     if not r:
         raise MemoryError("oracle allocation failed")
     try:

@@ -21,13 +21,23 @@
  *    include_output is set (zero level set of the output, Sec. 5.4).
  *  - Sign entries are stored as int8: +1, 0, -1.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no FMA contraction).
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -fPIC -shared (no FMA
+ * contraction). pcxo_set_threads(n) spreads the per-vertex loops (the forward
+ * pass at the layer start, the evaluation of a neuron at every vertex, the new
+ * vertices of a step) over n threads; each vertex's arithmetic is the same
+ * sequential expression whatever the thread count, so the result is too. The
+ * default is one thread.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int g_threads = 1;
+
+void pcxo_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
 
 #define PCXO_OK 0
 #define PCXO_ERR_INVALID (-1)
@@ -260,8 +270,11 @@ static pcxo_result *extract_core(const pcxo_net *net, int m, long nv, const doub
     memcpy(Ed, E0, sizeof(int32_t) * (size_t)E * 2);
 
     double *Hm = NULL;   /* memoised h^(l-1)(v) for the layer being subdivided */
-    double *tmp = (double *)malloc(sizeof(double) * (size_t)maxw);
-    double *tmp2 = (double *)malloc(sizeof(double) * (size_t)maxw);
+    const int nth = g_threads;
+    /* forward-pass scratch: two rows of the widest layer per thread */
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)maxw * 2 * (size_t)nth);
+    if (!tmp) { free(X); free(S); free(Ed); fail(r, PCXO_ERR_OOM, "oom"); return r; }
+    double *tmp2 = NULL;
     double *zv = NULL;   /* pre-activation of the current neuron at each vertex */
     long capZ = 0;
     int32_t *spl = NULL; long capSpl = 0;
@@ -283,7 +296,11 @@ static pcxo_result *extract_core(const pcxo_net *net, int m, long nv, const doub
         long capH = capV;
         Hm = (double *)malloc(sizeof(double) * (size_t)capH * nin);
         if (!Hm) { status = PCXO_ERR_OOM; why = "oom"; break; }
-        for (long v = 0; v < V; ++v) hidden_at(net, X + v * D, l - 1, Hm + v * nin, tmp, tmp2);
+#pragma omp parallel for num_threads(nth) schedule(static)
+        for (long v = 0; v < V; ++v) {
+            double *t1 = tmp + (size_t)maxw * 2 * (size_t)omp_get_thread_num();
+            hidden_at(net, X + v * D, l - 1, Hm + v * nin, t1, t1 + maxw);
+        }
 
         for (int i = 0; i < nl && status == PCXO_OK; ++i, ++step) {
             const int n = entry_base + i; /* entry of this neuron in the sign-vector */
@@ -292,25 +309,53 @@ static pcxo_result *extract_core(const pcxo_net *net, int m, long nv, const doub
             /* Steps 1-2: evaluate the pre-activation at every vertex, take its sign.
              * Genericity (Sec. 3.2, 3.4, 4.2.1): no old vertex lies on H. */
             if (capZ < V) { free(zv); capZ = capV; zv = (double *)malloc(sizeof(double) * (size_t)capZ); }
+            int zero_hit = 0;
+            double margin = r->min_margin;
+#pragma omp parallel for num_threads(nth) schedule(static) reduction(min : margin) reduction(| : zero_hit)
             for (long v = 0; v < V; ++v) {
                 double acc = 0.0;
                 const double *h = Hm + v * nin;
                 for (int k = 0; k < nin; ++k) acc += W[(long)i * nin + k] * h[k];
                 double z = acc + b[mutation == 5 ? (i + 1) % nl : i];
                 zv[v] = z;
-                if (z == 0.0) { status = PCXO_ERR_DEGENERATE; why = "vertex on a hyperplane (non-generic)"; break; }
-                if (fabs(z) < r->min_margin) r->min_margin = fabs(z);
+                if (z == 0.0) { zero_hit = 1; continue; }
+                if (fabs(z) < margin) margin = fabs(z);
                 S[v * M + n] = z > 0.0 ? 1 : -1;
             }
-            if (status != PCXO_OK) break;
-            /* Step 3: splitting edges have endpoints of opposite sign */
+            r->min_margin = margin;
+            if (zero_hit) { status = PCXO_ERR_DEGENERATE; why = "vertex on a hyperplane (non-generic)"; break; }
+            /* Step 3: splitting edges have endpoints of opposite sign, listed in
+             * edge order (each thread takes one contiguous range of the edges,
+             * counts its matches, then writes them after those of the ranges
+             * before it) */
             long ns = 0;
-            for (long e = 0; e < E; ++e) {
-                if (S[(long)Ed[2 * e] * M + n] != S[(long)Ed[2 * e + 1] * M + n]) {
-                    if (ns == capSpl) { capSpl = capSpl ? 2 * capSpl : 1024; spl = (int32_t *)xrealloc(spl, sizeof(int32_t) * (size_t)capSpl); }
-                    spl[ns++] = (int32_t)e;
+            long cnt[nth + 1];
+#pragma omp parallel num_threads(nth)
+            {
+                const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+                const long e0 = E * t / nt, e1 = E * (t + 1) / nt;
+                long c = 0;
+                for (long e = e0; e < e1; ++e)
+                    c += S[(long)Ed[2 * e] * M + n] != S[(long)Ed[2 * e + 1] * M + n];
+                cnt[t + 1] = c;
+#pragma omp barrier
+#pragma omp single
+                {
+                    cnt[0] = 0;
+                    for (int k = 0; k < nt; ++k) cnt[k + 1] += cnt[k];
+                    ns = cnt[nt];
+                    if (ns > capSpl) {
+                        capSpl = ns + ns / 2 + 1024;
+                        spl = (int32_t *)xrealloc(spl, sizeof(int32_t) * (size_t)capSpl);
+                    }
+                }
+                if (spl) {
+                    long pos = cnt[t];
+                    for (long e = e0; e < e1; ++e)
+                        if (S[(long)Ed[2 * e] * M + n] != S[(long)Ed[2 * e + 1] * M + n]) spl[pos++] = (int32_t)e;
                 }
             }
+            if (ns > 0 && !spl) { status = PCXO_ERR_OOM; why = "oom"; break; }
             r->steps[4 * step + 2] = ns;
             /* grow vertex / edge storage */
             if (V + ns > capV) {
@@ -334,6 +379,8 @@ static pcxo_result *extract_core(const pcxo_net *net, int m, long nv, const doub
              * and inherits the rest (join of the endpoints). The edge is replaced by
              * E+ and E-. */
             const long V0 = V, E0 = E;
+            int conflict_hit = 0;
+#pragma omp parallel for num_threads(nth) schedule(static) reduction(| : conflict_hit)
             for (long s = 0; s < ns; ++s) {
                 long e = spl[s];
                 int32_t a = Ed[2 * e], bq = Ed[2 * e + 1];
@@ -354,12 +401,13 @@ static pcxo_result *extract_core(const pcxo_net *net, int m, long nv, const doub
                 }
                 S[x0 * M + n] = 0;
                 for (int k = n + 1; k < M; ++k) S[x0 * M + k] = 0; /* set when those neurons are processed */
-                if (conflict) { status = PCXO_ERR_DEGENERATE; why = "sign conflict on an edge"; break; }
-                hidden_at(net, X + x0 * D, l - 1, Hm + x0 * nin, tmp, tmp2);
+                if (conflict) { conflict_hit = 1; continue; }
+                double *t1 = tmp + (size_t)maxw * 2 * (size_t)omp_get_thread_num();
+                hidden_at(net, X + x0 * D, l - 1, Hm + x0 * nin, t1, t1 + maxw);
                 Ed[2 * e] = a; Ed[2 * e + 1] = (int32_t)x0;          /* one half keeps the slot */
                 Ed[2 * (E0 + s)] = (int32_t)x0; Ed[2 * (E0 + s) + 1] = bq; /* the other is appended */
             }
-            if (status != PCXO_OK) break;
+            if (conflict_hit) { status = PCXO_ERR_DEGENERATE; why = "sign conflict on an edge"; break; }
             V = V0 + ns; E = E0 + ns;
             /* Step 5 (Sec. 4.2.2): perturb each splitting edge to its parent 2-faces
              * (Sec. 4.1: every zero to + and -, boundary zeros only to +). Each

@@ -485,6 +485,11 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     // growth path)
     const char *small_env = getenv("PCX_SMALL_START");
     const bool small_start = small_env && small_env[0] == '1';
+    // (PCX_FULL_GRIDS=1 launches every step's compaction, split and pairing with
+    // their largest grids, the launch shape of the big steps of large complexes:
+    // a test hook that runs a complex the oracle can check through that shape)
+    const char *fg_env = getenv("PCX_FULL_GRIDS");
+    const bool full_grids = fg_env && fg_env[0] == '1';
     size_t Vinit = std::max<size_t>({V0, 1024, small_start ? 0 : (size_t)mlp->hintV.load()});
     size_t Einit = std::max<size_t>({E0, 4096, small_start ? 0 : (size_t)mlp->hintE.load()});
     size_t Sinit = small_start ? 0 : (size_t)mlp->hintS.load();
@@ -712,7 +717,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
                     }
                 }
             }
-            blocks = split_blocks((int)std::min<int64_t>(Sgrid, INT32_MAX), N);
+            blocks = split_blocks(full_grids ? INT32_MAX : (int)std::min<int64_t>(Sgrid, INT32_MAX), N);
         }
         StepGeom g;
         g.D = D;
@@ -743,7 +748,8 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             launch_gather(x.b, (int)E, par, st);
         } else {
             if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-            launch_select(x.b, (uint16_t)j, par, select_grid(lagged ? std::max(Eseen, E) : E), st);
+            launch_select(x.b, (uint16_t)j, par, full_grids ? kSelBlocks : select_grid(lagged ? std::max(Eseen, E) : E),
+                          st);
         }
         if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
         HIPCHK(hipGetLastError());
@@ -762,7 +768,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             prevE = E;
             prevS = S;
             if ((rc = grow_for(V, E, S, 1, (size_t)S))) return rc;
-            blocks = split_blocks((int)S, N);
+            blocks = split_blocks(full_grids ? INT32_MAX : (int)S, N);
         }
         g.Vcap = (int)std::min<size_t>(x.Vcap, INT32_MAX);
         g.Ecap = (int)std::min<size_t>(x.Ecap, INT32_MAX);
@@ -773,7 +779,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         HIPCHK(hipGetLastError());
         if (lagged) {
             if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
-            launch_hash_pair(x.b, g, pair_grid(Sgrid * x.P), st);
+            launch_hash_pair(x.b, g, full_grids ? kSelBlocks : pair_grid(Sgrid * x.P), st);
             if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
             HIPCHK(hipGetLastError());
         } else if (S * x.P > 0) {

@@ -48,6 +48,7 @@ struct Job {
     std::shared_ptr<BatchHolder> batch;
     int bidx = -1;
     int64_t V = 0, E = 0, splits = 0;
+    int D = 0, Wd = 0;  // row sizes of the result (Wd counts the output word with include_output)
 };
 
 }  // namespace
@@ -120,6 +121,8 @@ void worker_loop(pcx_server *s, int w) {
             j->V = cx->V;
             j->E = cx->E;
             j->splits = cx->total_splits;
+            j->D = cx->D;
+            j->Wd = cx->Wd;
         }
         finish(s, j);
     }
@@ -203,6 +206,8 @@ void sched_loop(pcx_server *s) {
                     j->V = inf.V;
                     j->E = inf.E;
                     j->splits = inf.total_splits;
+                    j->D = inf.D;
+                    j->Wd = inf.Wd;
                 } else {
                     j->err = pcx_last_error();
                 }
@@ -270,6 +275,8 @@ int pcx_server_submit(pcx_server *s, const pcx_mlp *mlp, const double *lo, const
         ZS = std::max(ZS, mlp->widths[l]);
         if (mlp->widths[l] > kMaxWidth) fits = false;
     }
+    job->D = D;
+    job->Wd = Wd;
     const double pv = predict_vertices(D, N);
     job->small = fits && Wd <= kBatchMaxWords && pv <= (double)s->opts.small_vertices;
     // rows (coordinates, signs, pre-activations) and ~(D+1) edges per vertex
@@ -294,6 +301,8 @@ static int fill_result(Job *j, pcx_server_result *r) {
     r->E = j->E;
     r->total_splits = j->splits;
     r->batched = j->small ? 1 : 0;
+    r->D = j->D;
+    r->Wd = j->Wd;
     if (j->status != PCX_PENDING) {
         r->latency_ms = std::chrono::duration<double, std::milli>(j->t_done - j->t_submit).count();
         r->queue_ms = std::chrono::duration<double, std::milli>(j->t_admit - j->t_submit).count();

@@ -67,7 +67,8 @@ class _ServerOpts(C.Structure):
 
 class _ServerResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("batched", C.c_int32), ("V", C.c_int64), ("E", C.c_int64),
-                ("total_splits", C.c_int64), ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
+                ("total_splits", C.c_int64), ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("D", C.c_int32), ("Wd", C.c_int32)]
 
 
 class _ServerSummary(C.Structure):
@@ -477,11 +478,8 @@ class Server:
         r = self.wait(ticket)
         if r["status"] != PCX_OK:
             raise PcxError(r["status"], self.error(ticket))
-        mlp = self._keep[ticket][0]
-        D = mlp.D
-        Wd = 1
-        for n in mlp.widths[1:-1]:
-            Wd += (n + 31) // 32
+        # row sizes as the server reports them (the output word is counted with include_output)
+        D, Wd = r["D"], r["Wd"]
         X = np.empty((r["V"], D), np.float64)
         SG = np.empty((r["V"], Wd), np.uint64)
         Ed = np.empty((r["E"], 2), np.int32)

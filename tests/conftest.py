@@ -19,3 +19,19 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def oracle_threads() -> int:
+    """Threads for oracle work in a test: the CPUs this process may use, at most
+    16 (the host share of one GPU on the test machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_pool():
+    """A thread pool for independent oracle calls (the C oracle runs without the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    return ThreadPoolExecutor(max_workers=oracle_threads())

@@ -70,23 +70,42 @@ def test_batch_mixed_dims_output_fallback_and_degenerate(pcx, oracle_lib):
     bt.close()
 
 
-def test_batch_full_workload_counts(pcx, oracle_lib):
-    """All 4096 networks of the batched workload in one launch; a sample checked
-    bit-exactly against the per-step path and the oracle."""
+def test_batch_full_workload_every_network(pcx, oracle_lib):
+    """All 4096 networks of the batched workload in one launch: every network
+    bit-identical to its per-step extraction (values and numbering) and equal
+    to the oracle's complex in canonical form (signs and incidence exact,
+    coordinates within 1e-10)."""
+    from conftest import oracle_pool
     nets = wl.batch_nets()
     box = wl.cube(2)
+    pool = oracle_pool()
+    futs = [pool.submit(oracle_lib.extract, n, box.lo, box.hi) for n in nets]
     mlps = [pcx.MLP.from_net(n) for n in nets]
     bt = pcx.Batch(mlps, [(box.lo, box.hi)] * len(nets))
     st = bt.stats()
-    print(f"batch: {st}")
+    print(f"batch: {st}", flush=True)
     assert st.n == 4096 and st.degenerate == 0
-    rng = np.random.default_rng(7)
-    for i in rng.choice(4096, 48, replace=False):
-        got = bt.copy(int(i))
-        ref = plain(pcx, nets[i], box)
+    tot = [0, 0, 0]
+    for i, net in enumerate(nets):
+        got = bt.copy(i)
+        cx = pcx.extract(mlps[i], box.lo, box.hi)
+        ref = cx.copy()
+        cx.close()
         for a, b in zip(got, ref):
-            assert np.array_equal(a, b), f"network {i}"
-        r = oracle_lib.extract(nets[i], box.lo, box.hi)
-        info = bt.info(int(i))
+            assert a.shape == b.shape and np.array_equal(a, b), f"network {i} differs from the per-step path"
+        r = futs[i].result()
+        futs[i] = None  # results are held only until checked
+        X, SG, Ed = got
+        assert_same_complex((X, unpack_signs(SG, net.widths), Ed), (r.X, r.S, r.edges))
+        info = bt.info(i)
         assert (info.V, info.E, info.total_splits) == (r.V, r.E, int(r.steps[:, 2].sum()))
+        tot[0] += r.V
+        tot[1] += r.E
+        tot[2] += int(r.steps[:, 2].sum())
+        if i % 512 == 0:
+            print(f"[batch] {i + 1}/4096 networks checked", flush=True)
+    assert (st.total_V, st.total_E, st.total_splits) == tuple(tot)
+    pool.shutdown()
     bt.close()
+    for m in mlps:
+        m.close()

@@ -18,6 +18,10 @@ checked by parts the oracle or the mathematics fix exactly:
   cell (Sec. 3.5, 4.2.2);
 * on sampled vertices: the oracle's solve from the sign-vector lands on the same
   point, and the oracle's forward pass at the point reproduces the sign-vector.
+
+Whole-complex comparisons of the same network run on centred sub-boxes: the
+largest, [-0.125, 0.125]^3 (3.0M edges), also in the launch shape of the big
+steps (every grid at its maximum).
 """
 import numpy as np
 import pytest
@@ -207,3 +211,41 @@ def test_large_net_small_box_matches_oracle(oracle_lib, pcx):
     assert np.array_equal(steps, r.steps)
     assert_same_complex((X, S, Ed), (r.X, r.S, r.edges), coord_tol=1e-10)
     check_invariants(net, lo, hi, X, S, Ed, full=False)
+
+
+@pytest.mark.timeout(900)
+def test_large_net_subbox_whole_on_full_grids(oracle_lib, pcx, monkeypatch):
+    """The same network on the centred box [-0.125, 0.125]^3 (1.0M vertices,
+    3.0M edges, up to 17K splits and 68K 2-face key slots in a step), every
+    layer subdivided, compared whole with the oracle. The extraction runs twice:
+    with the launch shapes chosen for these step sizes, and with every step's
+    compaction, split and pairing on their largest grids (1024 compaction and
+    pairing workgroups, 16384 split workgroups: the shape of the bench's big
+    steps); both give the same arrays."""
+    from conftest import oracle_pool, oracle_threads
+    net = wl.plain_large()
+    lo, hi = np.full(3, -0.125), np.full(3, 0.125)
+    pool = oracle_pool()
+    fut = pool.submit(oracle_lib.extract, net, lo, hi, False, 0, False, oracle_threads())
+    m = pcx.MLP.from_net(net)
+    cx = pcx.extract(m, lo, hi)
+    base = cx.copy()
+    cx.close()
+    monkeypatch.setenv("PCX_FULL_GRIDS", "1")
+    cx = pcx.extract(m, lo, hi)
+    X, SG, Ed = cx.copy()
+    steps = cx.steps()
+    cx.close()
+    monkeypatch.delenv("PCX_FULL_GRIDS")
+    m.close()
+    for a, b in zip((X, SG, Ed), base):
+        assert a.shape == b.shape and np.array_equal(a, b), "launch shape changed the result"
+    print(f"[subbox] V={len(X)} E={len(Ed)} largest step {steps[:, 2].max()} splits, "
+          f"{steps[:, 3].max()} key slots", flush=True)
+    r = fut.result()
+    pool.shutdown()
+    assert len(Ed) >= 2_000_000
+    assert np.array_equal(steps, r.steps)
+    S = unpack_signs(SG, net.widths)
+    del SG, base
+    assert_same_complex((X, S, Ed), (r.X, r.S, r.edges), coord_tol=1e-10)
