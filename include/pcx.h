@@ -87,6 +87,10 @@ typedef struct {
     int64_t total_pairs;    /* sum over steps of intersecting edges (step 5) */
     uint64_t peak_bytes;    /* device bytes held at the peak of the extraction */
     double time_ms;         /* device time of the extraction (HIP events, weights resident) */
+    int32_t exact_steps;    /* steps whose 2-face pairing was redone by the exact pass (a hash
+                               collision, or a step with more than 2^24 - 2 key slots); the result
+                               is the same complex either way */
+    int32_t reserved;
 } pcx_info;
 
 const char *pcx_last_error(void);

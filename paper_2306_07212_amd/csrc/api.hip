@@ -70,10 +70,10 @@ struct Extraction {
     int timing_mask = 0;
     Arena arena;
     Bufs b{};
-    size_t Vcap = 0, Ecap = 0, Scap = 0, Kcap = 0, Hcap = 0;
+    size_t Vcap = 0, Ecap = 0, Scap = 0, Kcap = 0, Hcap = 0, Xcap = 0;
     int pair_mode = PAIR_HASH;
-    HEntry *HT[2] = {nullptr, nullptr};  // 2-face hash tables, alternating by step
-    size_t Tcap = 0;                     // entries per table
+    unsigned long long *HT[2] = {nullptr, nullptr};  // 2-face hash tables, alternating by step
+    size_t Tcap = 0;                                 // words per table
     bool tape = false;
     bool prune = false;
     int D = 0, Wd = 0, ZS = 0, P = 0;
@@ -206,6 +206,16 @@ struct Extraction {
         }
         return PCX_OK;
     }
+    int ensure_hist(size_t K) {
+        size_t h = (size_t)kSortBins * ((K + kSortTile - 1) / kSortTile + 1);
+        if (h > Hcap) {
+            size_t nc = std::max(h, Hcap * 2);
+            int rc;
+            if ((rc = grow_scratch(b.HIST, Hcap, nc))) return rc;
+            Hcap = nc;
+        }
+        return PCX_OK;
+    }
     int ensure_step(size_t S, size_t K) {
         int rc;
         if (S > Scap) return fail(PCX_ERR_DEVICE, "split list smaller than the split count");
@@ -216,11 +226,14 @@ struct Extraction {
                 if ((rc = grow_scratch(b.K32b, Kcap, nc))) return rc;
                 if ((rc = grow_scratch(b.VALa, Kcap, nc))) return rc;
                 if ((rc = grow_scratch(b.VALb, Kcap, nc))) return rc;
+                if ((rc = grow_scratch(b.FULL, Kcap, nc))) return rc;
             }
-            if ((rc = grow_scratch(b.FULL, Kcap, nc))) return rc;
             if ((rc = grow_scratch(b.PINFO, Kcap, nc))) return rc;
-            if (pair_mode == PAIR_HASH && (rc = grow_scratch(b.PART, Kcap, nc))) return rc;
+            // partner records start untagged (no step has written them)
+            if ((rc = grow_scratch(b.PART, Kcap, nc))) return rc;
+            launch_fill64(b.PART, nc, 0ull, st);
             Kcap = nc;
+            Xcap = 0;  // the exact pass's keys follow the key capacity
         }
         if (pair_mode == PAIR_HASH) {
             size_t tc = 256;
@@ -228,20 +241,28 @@ struct Extraction {
             if (tc > Tcap) {
                 for (int t = 0; t < 2; ++t) {
                     if ((rc = grow_scratch(HT[t], Tcap, tc))) return rc;
-                    HIPCHK(hipMemsetAsync(HT[t], 0, tc * sizeof(HEntry), st));
+                    launch_fill64(reinterpret_cast<uint64_t *>(HT[t]), tc, 0ull, st);
                 }
                 Tcap = tc;
                 tables_reset = true;
             }
             return PCX_OK;
         }
-        size_t h = (size_t)kSortBins * ((K + kSortTile - 1) / kSortTile + 1);
-        if (h > Hcap) {
-            size_t nc = std::max(h, Hcap * 2);
-            if ((rc = grow_scratch(b.HIST, Hcap, nc))) return rc;
-            Hcap = nc;
+        return ensure_hist(K);
+    }
+    // the exact pass of a step with K key slots (K <= Kcap)
+    int ensure_exact(size_t K) {
+        int rc;
+        if (Xcap < Kcap) {
+            if ((rc = grow_scratch(b.K64a, Xcap, Kcap))) return rc;
+            if ((rc = grow_scratch(b.K64b, Xcap, Kcap))) return rc;
+            if (pair_mode == PAIR_HASH) {
+                if ((rc = grow_scratch(b.VALa, Xcap, Kcap))) return rc;
+                if ((rc = grow_scratch(b.VALb, Xcap, Kcap))) return rc;
+            }
+            Xcap = Kcap;
         }
-        return PCX_OK;
+        return ensure_hist(K);
     }
 };
 
@@ -490,6 +511,15 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     // a test hook that runs a complex the oracle can check through that shape)
     const char *fg_env = getenv("PCX_FULL_GRIDS");
     const bool full_grids = fg_env && fg_env[0] == '1';
+    // (PCX_DEBUG_HASH_BITS=b keeps only b bits of every 2-face hash, and
+    // PCX_DEBUG_EXACT_BITS=b of the exact pass's sort keys: collisions on
+    // purpose, test hooks for the exact pass and its grouping)
+    auto env_bits = [](const char *name) {
+        const char *v = getenv(name);
+        const int b = v ? atoi(v) : 64;
+        return b >= 1 && b < 64 ? b : 64;
+    };
+    const int hbits = env_bits("PCX_DEBUG_HASH_BITS"), fbits = env_bits("PCX_DEBUG_EXACT_BITS");
     size_t Vinit = std::max<size_t>({V0, 1024, small_start ? 0 : (size_t)mlp->hintV.load()});
     size_t Einit = std::max<size_t>({E0, 4096, small_start ? 0 : (size_t)mlp->hintE.load()});
     size_t Sinit = small_start ? 0 : (size_t)mlp->hintS.load();
@@ -510,6 +540,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         h[CTR_V] = (int)V0;
         h[CTR_E] = (int)E0;
         h[CTR_FAIL] = 0x7fffffff;
+        h[CTR_PFAIL] = 0x7fffffff;
         std::memcpy(x.hctr, h, sizeof h);
         HIPCHK(hipMemcpyAsync(x.b.CTR, x.hctr, sizeof h, hipMemcpyHostToDevice, st));
     }
@@ -586,24 +617,87 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         }
         return PCX_OK;
     };
-    // after a drain: a step that found the storage too small is redone from its
-    // compaction once the storage fits it; returns that step, or -1
-    auto recover = [&](int &fstep) -> int {
-        fstep = -1;
-        const int flags = x.hctr[CTR_FLAGS];
-        if (!flags) return PCX_OK;
-        if (flags != FLAG_CAPACITY) return degenerate_message(flags & ~FLAG_CAPACITY);
-        const int f = x.hctr[CTR_FAIL];
-        if (f < 0 || f >= n_steps) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
-        const int64_t Sf = x.hctr[CTR_S], Vf = x.hctr[CTR_V + (f & 1)], Ef = x.hctr[CTR_E + (f & 1)];
-        V = Vf;  // a redone first step of a layer rescans the edges from these counts
-        E = Ef;
+    // the geometry of neuron j of subdivided layer l (global step s)
+    auto geom = [&](int l, int j) {
+        const int s = step0[l] + j, par = s & 1;
+        StepGeom g{};
+        g.D = D;
+        g.Wd = Wd;
+        g.ZS = ZS;
+        g.Nl = mlp->widths[l + 1];
+        g.lw0 = lw[l];
+        g.lw1 = lw[l + 1];
+        g.j = j;
+        g.wn = lw[l] + (j >> 5);
+        g.bn = 2 * (j & 31);
+        g.P = x.P;
+        // in the last subdivided layer nothing reads the processed columns again
+        g.zlo = (l == nsub - 1 && !x.tape) ? j + 1 : 0;
+        g.pair_mode = x.pair_mode;
+        g.hmask = 0;
+        g.HT = x.HT[par];
+        g.HTo = x.HT[par ^ 1];
+        g.step = s;
+        g.par = par;
+        g.nx8 = 1;
+        g.hkeep = hbits < 64 ? (1ull << hbits) - 1ull : ~0ull;
+        g.fbits = fbits;
+        g.Vcap = (int)std::min<size_t>(x.Vcap, INT32_MAX);
+        g.Ecap = (int)std::min<size_t>(x.Ecap, INT32_MAX);
+        g.Kcap = (int)std::min<size_t>(x.Kcap, INT32_MAX);
+        return g;
+    };
+    auto layer_of = [&](int s) { return (int)(std::upper_bound(step0.begin(), step0.end(), s) - step0.begin()) - 1; };
+    int exact_steps = 0;
+    // after a drain, act on the device flags. A step that found the storage too
+    // small is redone from its compaction once the storage fits it (next = that
+    // step). A step whose pairing failed has its pairing redone by the exact
+    // pass, and work resumes after it (next = the following step; fresh: that
+    // step starts a layer not yet begun, or is the end). next = -1: nothing to do.
+    auto recover = [&](int &next, bool &fresh) -> int {
+        next = -1;
+        fresh = false;
+        const int flags = x.hctr[CTR_FLAGS], pflags = x.hctr[CTR_PFLAGS];
+        if (!flags && !pflags) return PCX_OK;
+        if (flags & ~FLAG_CAPACITY) return degenerate_message((flags & ~FLAG_CAPACITY) | pflags);
         int r;
-        // exactly what step f needs: each array that is short grows by half
-        if ((r = grow_for(Vf, Ef, Sf, 1))) return r;
-        if ((r = x.put_ctr(CTR_FAIL, 0x7fffffff)) || (r = x.put_ctr(CTR_FLAGS, 0))) return r;
-        fstep = f;
-        ++redone;
+        if (flags) {
+            // (a step that found the storage too small wrote nothing, and no later step ran)
+            const int f = x.hctr[CTR_FAIL];
+            if (f < 0 || f >= n_steps) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
+            const int64_t Sf = x.hctr[CTR_S], Vf = x.hctr[CTR_V + (f & 1)], Ef = x.hctr[CTR_E + (f & 1)];
+            V = Vf;  // a redone first step of a layer rescans the edges from these counts
+            E = Ef;
+            // exactly what step f needs: each array that is short grows by half
+            if ((r = grow_for(Vf, Ef, Sf, 1))) return r;
+            if ((r = x.put_ctr(CTR_FAIL, 0x7fffffff)) || (r = x.put_ctr(CTR_FLAGS, 0))) return r;
+            next = f;
+            ++redone;
+            return PCX_OK;
+        }
+        if (pflags & ~kPairFlags) return fail(PCX_ERR_DEVICE, "internal error: unknown pairing flag");
+        // the pairing of step pf failed; its split is complete and no later step ran
+        const int pf = x.hctr[CTR_PFAIL];
+        if (pf < 0 || pf >= n_steps) return fail(PCX_ERR_DEVICE, "internal error: bad failing pairing step");
+        const int lf = layer_of(pf);
+        StepGeom g = geom(lf, pf - step0[lf]);
+        const int64_t nslots = (int64_t)x.hctr[CTR_S] * x.P;
+        if (nslots > (int64_t)x.Kcap) return fail(PCX_ERR_DEVICE, "internal error: key slots beyond the storage");
+        if ((r = x.put_ctr(CTR_PFLAGS, 0)) || (r = x.put_ctr(CTR_PFAIL, 0x7fffffff))) return r;
+        if ((r = x.ensure_exact((size_t)nslots))) return r;
+        const int grid = full_grids ? kSelBlocks : pair_grid(nslots);
+        launch_exact_pair(x.b, g, (int)nslots, grid, st);
+        HIPCHK(hipGetLastError());
+        if ((r = x.drain())) return r;
+        if (x.hctr[CTR_FLAGS] || x.hctr[CTR_PFLAGS])
+            return degenerate_message(x.hctr[CTR_FLAGS] | x.hctr[CTR_PFLAGS]);
+        ++exact_steps;
+        if (verbose) {
+            fprintf(stderr, "[pcx] step %d paired by the exact pass (flags %d)\n", pf, pflags);
+            fflush(stderr);
+        }
+        next = pf + 1;
+        fresh = next == n_steps || next == step0[layer_of(next)];
         return PCX_OK;
     };
 
@@ -614,10 +708,16 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             // layer start (or the end): every enqueued step is done
             if ((rc = x.drain())) return rc;
             int f;
-            if ((rc = recover(f))) return rc;
+            bool fresh;
+            if ((rc = recover(f, fresh))) return rc;
             if (f >= 0) {
-                // the failed step belongs to the layer just finished
-                l = (int)(std::upper_bound(step0.begin(), step0.end(), f) - step0.begin()) - 1;
+                if (fresh) {
+                    // resume at the start of a layer (or the end): this layer start again
+                    l = f >= n_steps ? nsub : layer_of(f);
+                    continue;
+                }
+                // the step to continue from belongs to the layer just finished
+                l = layer_of(f);
                 j = f - step0[l];
                 started = true;
                 continue;
@@ -704,13 +804,15 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
                     x.snap_at[other] = -1;
                     Sgrid = std::max<int64_t>(Sgrid, c[CTR_SMAX] + c[CTR_SMAX] / 4 + 64);
                     Eseen = std::max<int64_t>({Eseen, c[CTR_E], c[CTR_E + 1]});
-                    if (c[CTR_FLAGS]) {
-                        // stop running ahead: exact counts, then redo or report
+                    if (c[CTR_FLAGS] || c[CTR_PFLAGS]) {
+                        // stop running ahead: exact counts, then redo, resume or report
                         if ((rc = x.drain())) return rc;
                         int f;
-                        if ((rc = recover(f))) return rc;
+                        bool fresh;
+                        if ((rc = recover(f, fresh))) return rc;
                         if (f >= 0) {
-                            if (f < step0[l] || f > s) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
+                            if (fresh || f < step0[l] || f > s)
+                                return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
                             j = f - step0[l];
                             continue;
                         }
@@ -719,44 +821,33 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             }
             blocks = split_blocks(full_grids ? INT32_MAX : (int)std::min<int64_t>(Sgrid, INT32_MAX), N);
         }
-        StepGeom g;
-        g.D = D;
-        g.Wd = Wd;
-        g.ZS = ZS;
-        g.Nl = N;
-        g.lw0 = lw[l];
-        g.lw1 = lw[l + 1];
-        g.j = j;
-        g.wn = lw[l] + (j >> 5);
-        g.bn = 2 * (j & 31);
-        g.P = x.P;
-        // in the last subdivided layer nothing reads the processed columns again
-        g.zlo = (l == nsub - 1 && !x.tape) ? j + 1 : 0;
-        g.pair_mode = x.pair_mode;
-        g.hmask = 0;
-        g.HT = x.HT[par];
-        g.HTo = x.HT[par ^ 1];
-        g.step = s;
-        g.par = par;
-        g.nx8 = 1;
+        StepGeom g = geom(l, j);
         if (j == 0) {
             // the layer's first crossings; its scan is also the first pass of this step's compaction
             if ((rc = x.mark(PCX_K_NEXT, true))) return rc;
-            launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, par, st);
+            launch_next_all(x.b, (int)V, Wd, lw[l], lw[l + 1], (int)E, par, s, st);
             if ((rc = x.mark(PCX_K_NEXT, false))) return rc;
             if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-            launch_gather(x.b, (int)E, par, st);
+            launch_gather(x.b, (int)E, par, s, st);
         } else {
             if ((rc = x.mark(PCX_K_SELECT, true))) return rc;
-            launch_select(x.b, (uint16_t)j, par, full_grids ? kSelBlocks : select_grid(lagged ? std::max(Eseen, E) : E),
-                          st);
+            launch_select(x.b, (uint16_t)j, par, s,
+                          full_grids ? kSelBlocks : select_grid(lagged ? std::max(Eseen, E) : E), st);
         }
         if ((rc = x.mark(PCX_K_SELECT, false))) return rc;
         HIPCHK(hipGetLastError());
         int64_t S = 0;
         if (!lagged) {
             if ((rc = x.drain())) return rc;
-            if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
+            int f;
+            bool fresh;
+            if ((rc = recover(f, fresh))) return rc;
+            if (f >= 0) {
+                // the previous step's pairing was redone: this step's compaction again
+                if (fresh || f < step0[l] || f > s) return fail(PCX_ERR_DEVICE, "internal error: bad failing step");
+                j = f - step0[l];
+                continue;
+            }
             S = x.hctr[CTR_S];
             E = x.hctr[CTR_E + par];
             V = x.hctr[CTR_V + par];
@@ -769,17 +860,16 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
             prevS = S;
             if ((rc = grow_for(V, E, S, 1, (size_t)S))) return rc;
             blocks = split_blocks(full_grids ? INT32_MAX : (int)S, N);
+            g = geom(l, j);  // capacities may have grown
         }
-        g.Vcap = (int)std::min<size_t>(x.Vcap, INT32_MAX);
-        g.Ecap = (int)std::min<size_t>(x.Ecap, INT32_MAX);
-        g.Kcap = (int)std::min<size_t>(x.Kcap, INT32_MAX);
+        const int pgrid = full_grids ? kSelBlocks : pair_grid(lagged ? Sgrid * x.P : S * x.P);
         hipEvent_t es, ee;
         if ((rc = x.launch_events(PCX_K_SPLIT, es, ee))) return rc;
         launch_split(x.b, g, blocks, st, es, ee);
         HIPCHK(hipGetLastError());
         if (lagged) {
             if ((rc = x.mark(PCX_K_PAIR, true))) return rc;
-            launch_hash_pair(x.b, g, full_grids ? kSelBlocks : pair_grid(Sgrid * x.P), st);
+            launch_hash_pair(x.b, g, pgrid, st);
             if ((rc = x.mark(PCX_K_PAIR, false))) return rc;
             HIPCHK(hipGetLastError());
         } else if (S * x.P > 0) {
@@ -799,7 +889,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     }
     HIPCHK(hipEventRecord(t1, st));
     if ((rc = x.drain())) return rc;
-    if (x.hctr[CTR_FLAGS]) return degenerate_message(x.hctr[CTR_FLAGS]);
+    if (x.hctr[CTR_FLAGS] || x.hctr[CTR_PFLAGS]) return degenerate_message(x.hctr[CTR_FLAGS] | x.hctr[CTR_PFLAGS]);
     V = x.hctr[CTR_V + (n_steps & 1)];
     E = x.hctr[CTR_E + (n_steps & 1)];
     int64_t total_splits = 0, Smax = 0;
@@ -823,8 +913,8 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         Ebound = std::max<int64_t>(Ebound, steps[(size_t)t * 4 + 1] + St * std::max(1, D));
     }
     if (verbose) {
-        fprintf(stderr, "[pcx] done: V=%lld E=%lld steps redone after growing the storage: %d\n", (long long)V,
-                (long long)E, redone);
+        fprintf(stderr, "[pcx] done: V=%lld E=%lld steps redone after growing the storage: %d, paired by the exact "
+                "pass: %d\n", (long long)V, (long long)E, redone, exact_steps);
         fflush(stderr);
     }
     float ms = 0.f;
@@ -865,6 +955,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     int64_t pairs = 0;
     for (int s = 0; s < n_steps; ++s) pairs += cx->steps[(size_t)s * 4 + 3] / 2;
     cx->total_pairs = pairs;
+    cx->exact_steps = exact_steps;
     cx->peak = x.arena.peak;
     cx->time_ms = ms;
     for (int k = 0; k < PCX_K_COUNT; ++k) {
@@ -951,6 +1042,7 @@ int pcx_complex_info(const pcx_complex *cx, pcx_info *info) {
     info->total_pairs = cx->total_pairs;
     info->peak_bytes = cx->peak;
     info->time_ms = cx->time_ms;
+    info->exact_steps = cx->exact_steps;
     return PCX_OK;
 }
 

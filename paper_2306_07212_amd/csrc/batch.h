@@ -11,7 +11,10 @@ constexpr int kBatchMaxLayers = 8;  // affine layers per network in a batch
 constexpr int kBatchMaxD = 8;       // input dimension in a batch
 constexpr int kBatchMaxWords = 64;  // sign-row words per vertex in a batch
 
-enum { BATCH_OK = 0, BATCH_OVERFLOW = 1, BATCH_POOL = 2, BATCH_DEGENERATE = 3, BATCH_INTERNAL = 4 };
+// BATCH_RETRY: the 2-face pairing failed in the batched kernel (a hash
+// collision, or a degenerate face); the per-step path, whose exact pass tells
+// the two apart, extracts the network instead
+enum { BATCH_OK = 0, BATCH_OVERFLOW = 1, BATCH_POOL = 2, BATCH_DEGENERATE = 3, BATCH_INTERNAL = 4, BATCH_RETRY = 5 };
 
 struct BatchNet {
     const double *Wt[kBatchMaxLayers];  // transposed weights, [N_{l-1}][N_l]
@@ -42,14 +45,16 @@ struct BatchArgs {
     unsigned long long *pool;  // used: [0] coordinate doubles, [1] sign words, [2] edges
     unsigned long long capV, capSG, capE;
     BatchResult *res;
+    int hbits;         // bits of the 2-face hash kept (64; fewer only in tests)
 };
 
-// bytes of one workgroup arena: vertex region + edges (14 B) + keys (12 B)
-// + table + valid words + counters
+// bytes of one workgroup arena: vertex region + edges (14 B) + key slots
+// (partner record 8 B, perturbed entry 4 B) + table (8 B words) + valid words
+// + counters
 inline size_t batch_arena_bytes(size_t vbytes, int ecap, int kcap, uint32_t tcap) {
     size_t k = (size_t)kcap * 12;
     k += 256 - k % 256;
-    return vbytes + (size_t)ecap * 16 + k + (size_t)tcap * sizeof(HEntry) + kBatchMaxWords * 8 + 256;
+    return vbytes + (size_t)ecap * 16 + k + (size_t)tcap * sizeof(unsigned long long) + kBatchMaxWords * 8 + 256;
 }
 
 void launch_batch(const BatchArgs &A, int grid, hipStream_t st);

@@ -53,7 +53,8 @@ __device__ int block_select(const Bufs &b, int E, uint16_t target, int *s_w) {
     return run;
 }
 
-// Hash pairing by the whole workgroup: owners (smaller key slot) in slot order.
+// Hash pairing by the whole workgroup: the split recorded the pairs; owners
+// (smaller key slot) emit them in slot order.
 __device__ int block_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, int *s_w) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int run = 0;
@@ -63,7 +64,7 @@ __device__ int block_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int 
         uint32_t own = 0;
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i)
-            if (base + i < nslots && hash_owner(b, g, base + i, nslots, partner[i])) own |= 1u << i;
+            if (base + i < nslots && slot_owner(b, g, base + i, nslots, partner[i])) own |= 1u << i;
         const int cnt = __popc(own);
         int incl = cnt;
 #pragma unroll
@@ -94,7 +95,7 @@ template <int G, int NC>
 __device__ __forceinline__ void block_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S) {
     constexpr int groups = kThreads / G;
     const int lane = threadIdx.x % G, grp = threadIdx.x / G, half = (threadIdx.x & 63) / G;
-    for (int s = grp; s < S; s += groups) split_one<G, NC>(b, g, V0, E0, s, lane, half);
+    for (int s = grp; s < S; s += groups) split_one<G, NC>(b, g, V0, E0, s, lane, half, S * g.P);
 }
 
 __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b, GemmLds *gl, int *s_w,
@@ -123,10 +124,11 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
     b.NXT = (uint16_t *)(eb + (size_t)Ecap * 8);
     b.SPL = (int *)(eb + (size_t)Ecap * 10);
     char *kb = eb + (size_t)Ecap * 16;
-    b.FULL = (uint64_t *)kb;
+    b.PART = (uint64_t *)kb;
     b.PINFO = (uint32_t *)(kb + (size_t)Kcap * 8);
-    HEntry *table = (HEntry *)(kb + (size_t)Kcap * 12 + 256 - ((size_t)Kcap * 12) % 256);
-    uint64_t *valid = (uint64_t *)((char *)table + (size_t)A.tcap * sizeof(HEntry));
+    b.FULL = nullptr;
+    unsigned long long *table = (unsigned long long *)(kb + (size_t)Kcap * 12 + 256 - ((size_t)Kcap * 12) % 256);
+    uint64_t *valid = (uint64_t *)((char *)table + (size_t)A.tcap * sizeof(unsigned long long));
     b.CTR = (int *)(valid + kBatchMaxWords);
     b.VALID = valid;
     b.PQ = nullptr;
@@ -146,7 +148,9 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                 }
             valid[w] = v;
         }
-        if (t < CTR_COUNT) b.CTR[t] = 0;
+        if (t < CTR_COUNT) b.CTR[t] = t == CTR_PFAIL ? 0x7fffffff : 0;
+        // partner records of an earlier network in this arena: untagged again
+        for (int i = t; i < Kcap; i += kThreads) b.PART[i] = 0ull;
         // step 0: the box
         for (int i = t; i < V0 + E0; i += kThreads) {
             if (i < V0) {
@@ -171,6 +175,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
     }
     int V = V0, E = E0;
     long long splits = 0, pairs = 0;
+    int step = 0;  // neuron steps of this network so far (tags its partner records)
     for (int l = 0; l < nsub && status == BATCH_OK; ++l) {
         const int N = net.widths[l + 1], K = net.widths[l];
         // step 1 for the layer, in place, one 32-row tile at a time
@@ -192,7 +197,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             __syncthreads();
             break;
         }
-        for (int j = 0; j < N; ++j) {
+        for (int j = 0; j < N; ++j, ++step) {
             const int S = block_select(b, E, (uint16_t)j, s_w);
             if (S == 0) continue;
             uint32_t tsz = 256;
@@ -201,7 +206,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                 status = BATCH_OVERFLOW;
                 break;
             }
-            StepGeom g;
+            StepGeom g{};
             g.D = D;
             g.Wd = Wd;
             g.ZS = ZS;
@@ -217,14 +222,12 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             g.hmask = tsz - 1;
             g.zlo = 0;
             g.nx8 = 0;
+            g.step = step;
+            g.par = 0;
+            g.hkeep = A.hbits < 64 ? (1ull << A.hbits) - 1ull : ~0ull;
+            g.fbits = 64;
             if (P > 0) {
-                for (uint32_t i = t; i < tsz; i += kThreads) {
-                    HEntry z;
-                    z.key = 0ull;
-                    z.a = 0u;
-                    z.b = 0u;
-                    table[i] = z;
-                }
+                for (uint32_t i = t; i < tsz; i += kThreads) table[i] = 0ull;
                 __syncthreads();
             }
             if (N <= 32) block_split<32, 1>(b, g, V, E, S);
@@ -232,18 +235,28 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             else if (N <= 128) block_split<32, 4>(b, g, V, E, S);
             else block_split<32, 8>(b, g, V, E, S);
             __syncthreads();
+            // the pairing reads partner records other waves of this workgroup stored: past the L1
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             int np = 0;
             if (P > 0) np = block_pair(b, g, V, E + S, S * P, s_w);
             V += S;
             E += S + np;
             splits += S;
             pairs += np;
-            if (t == 0) s_misc[0] = __hip_atomic_load(&b.CTR[CTR_FLAGS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == 0) {
+                s_misc[0] = __hip_atomic_load(&b.CTR[CTR_FLAGS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_misc[1] = __hip_atomic_load(&b.CTR[CTR_PFLAGS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             __syncthreads();
-            const int flags = s_misc[0];
+            const int flags = s_misc[0], pflags = s_misc[1];
             __syncthreads();
             if (flags) {
                 status = (flags & FLAG_BOUNDS) ? BATCH_INTERNAL : BATCH_DEGENERATE;
+                break;
+            }
+            if (pflags) {
+                // a hash collision or a face not met twice: the per-step path decides exactly
+                status = BATCH_RETRY;
                 break;
             }
         }

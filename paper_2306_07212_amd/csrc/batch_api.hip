@@ -189,6 +189,12 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
         A.capSG = capSG;
         A.capE = capE;
         {
+            // (PCX_DEBUG_HASH_BITS: as in pcx_extract, collisions on purpose for tests)
+            const char *v = getenv("PCX_DEBUG_HASH_BITS");
+            const int hb = v ? atoi(v) : 64;
+            A.hbits = hb >= 1 && hb < 64 ? hb : 64;
+        }
+        {
             HIPCHK(hipMemcpyAsync((void *)A.nets, nets.data(), (size_t)n * sizeof(BatchNet), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync((void *)A.order, batched.data(), batched.size() * sizeof(int), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemsetAsync(A.pool, 0, 8 * sizeof(unsigned long long), st));
@@ -209,7 +215,7 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
         bt->wg_per_cu = wpc;
         for (int i : batched) {
             const int s = bt->res[i].status;
-            if (s == BATCH_OVERFLOW || s == BATCH_POOL) direct.push_back(i);
+            if (s == BATCH_OVERFLOW || s == BATCH_POOL || s == BATCH_RETRY) direct.push_back(i);
             else if (s == BATCH_INTERNAL) {
                 rc = fail(PCX_ERR_DEVICE, "internal error in the batched kernel");
                 goto fail_out;

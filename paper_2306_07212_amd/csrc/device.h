@@ -134,53 +134,71 @@ __device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, in
 
 // ----------------------------------------------- 2-face hash table
 //
-// Open addressing with linear probing on the full 64-bit key. The first
-// splitting edge to reach a 2-face claims the slot with a 64-bit CAS and
-// records its key slot in `a`; the second finds the key and records itself in
-// `b` (plain stores: only the key's CAS returns a value the split waits for).
-// A third arrival means the 2-face is not met by exactly two splitting edges
-// (Sec. 4.2.2): it overwrites `b`, and the slot left in neither field raises
-// FLAG_RUN when the entries are read.
-__device__ __forceinline__ void hash_insert(HEntry *T, uint32_t mask, uint64_t H, uint32_t u, int *ctr) {
-    uint32_t h = (uint32_t)H & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const unsigned long long prev = atomicCAS(&T[h].key, 0ull, (unsigned long long)H);
-        if (prev == 0ull) {
-            T[h].a = u + 1;
-            return;
-        }
-        if (prev == (unsigned long long)H) {
-            // a plain store: a third splitting edge on this 2-face would overwrite
-            // b, and the pass that reads the entries flags the slot left in neither
-            T[h].b = u + 1;
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-    raise_flag(ctr, FLAG_BOUNDS);  // table full: cannot happen at load factor <= 1/2
+// Open addressing with linear probing, one 64-bit word per splitting 2-face
+// (layout in internal.h). The first splitting edge to reach a face claims an
+// empty word with a CAS that publishes its key and its slot together; the
+// second finds the key in the value its own CAS returns, takes the partner's
+// slot from it and records the pair at once: each of the two slots gets a
+// record naming the other, tagged with the step. The pairing then checks that
+// every valid slot's record is fresh and mutual. A face met once leaves its
+// slot without a fresh record; a face reached a third time leaves a record the
+// partner does not return (a slot names one partner only); two faces that share
+// 39 key bits and a probe chain are paired and then fail the word-by-word
+// comparison. Each of these sends the step to the exact pass.
+
+// pairing failures: recorded with their step (the exact pass redoes that step)
+__device__ __forceinline__ void raise_pair_flag(int *ctr, int f, int step) {
+    atomicOr(&ctr[CTR_PFLAGS], f);
+    atomicMin(&ctr[CTR_PFAIL], step);
 }
 
-// Table words are read with workgroup-scope atomic loads, which skip the L1:
-// inside the persistent batched kernel the entries were last written (CAS on
-// the key, plain store of `b`) by other waves of the same workgroup, before
-// the barrier that ends the split phase (one CU: the writes are in its L2);
-// across the per-step kernels a launch boundary already orders them.
-__device__ __forceinline__ unsigned long long load_key(const HEntry *T, uint32_t h) {
-    return __hip_atomic_load(&T[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ uint32_t load_u32(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// the pair (u, p) of one 2-face: each slot's record names the other
+__device__ __forceinline__ void record_pair(const Bufs &b, const StepGeom &g, uint32_t u, uint32_t p, int nslots) {
+    if (p >= (uint32_t)nslots || p == u) {
+        raise_flag(b.CTR, FLAG_BOUNDS);
+        return;
+    }
+    const uint64_t tag = (uint64_t)(uint32_t)(g.step + 1) << 32;
+    b.PART[u] = tag | (uint64_t)(p + 1);
+    b.PART[p] = tag | (uint64_t)(u + 1);
 }
 
-__device__ __forceinline__ int hash_find(const HEntry *T, uint32_t mask, uint64_t H) {
-    uint32_t h = (uint32_t)H & mask;
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const unsigned long long k = load_key(T, h);
-        if (k == (unsigned long long)H) return (int)h;
-        if (k == 0ull) return -1;
-        h = (h + 1) & mask;
+__device__ __forceinline__ void hash_insert(const Bufs &b, const StepGeom &g, uint64_t H, uint32_t u, int nslots) {
+    const unsigned long long key = (H >> 25) & kKeyMask;
+    const unsigned long long mine = (key << kSlotBits) | (unsigned long long)(u + 1);
+    uint32_t h = (uint32_t)H & g.hmask;
+    for (uint32_t probe = 0; probe <= g.hmask; ++probe) {
+        const unsigned long long old = atomicCAS(&g.HT[h], 0ull, mine);
+        if (old == 0ull) return;  // first arrival: the second records the pair
+        if ((old >> kSlotBits) == key) {
+            record_pair(b, g, u, (uint32_t)(old & kSlotMask) - 1u, nslots);
+            return;
+        }
+        h = (h + 1) & g.hmask;
     }
-    return -1;
+    raise_flag(b.CTR, FLAG_BOUNDS);  // table full: cannot happen at load factor <= 1/2
+}
+
+// partner of valid key slot u from its record (-1: no fresh record)
+__device__ __forceinline__ int slot_partner(const Bufs &b, const StepGeom &g, int u, int nslots) {
+    const uint64_t r = b.PART[u];
+    const uint32_t p1 = (uint32_t)r;
+    if ((uint32_t)(r >> 32) != (uint32_t)(g.step + 1) || p1 == 0u || p1 - 1u >= (uint32_t)nslots) return -1;
+    return (int)(p1 - 1u);
+}
+
+// Key slot u at the pairing's check: true if u owns a pair (the smaller slot
+// of a mutual pair of fresh records). A valid slot without a fresh mutual
+// record is a pairing failure of the step.
+__device__ __forceinline__ bool slot_owner(const Bufs &b, const StepGeom &g, int u, int nslots, int &partner) {
+    if (b.PINFO[u] == kNoInfo) return false;
+    const int p = slot_partner(b, g, u, nslots);
+    if (p < 0 || slot_partner(b, g, p, nslots) != u) {
+        raise_pair_flag(b.CTR, FLAG_RUN, g.step);
+        return false;
+    }
+    partner = p;
+    return u < p;
 }
 
 // Verifies that key slots sa, sb name the same 2-face (their perturbed sign
@@ -208,7 +226,7 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
         const uint64_t fb = (Rb[w] & lt) | (w == wb ? cb : 0ull);
         diff |= fa ^ fb;
     }
-    if (diff) raise_flag(b.CTR, FLAG_VERIFY);
+    if (diff) raise_pair_flag(b.CTR, FLAG_VERIFY, g.step);
     // first crossing after the neuron: four words per round, loaded together
     int col = kNoCol;
     for (int w0 = g.wn; w0 < g.lw1 && col == kNoCol; w0 += 4) {
@@ -227,32 +245,6 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
         b.NX8[out] = col == kNoCol ? 0 : (uint8_t)col;  // col > j >= 0
     else
         b.NXT[out] = col == kNoCol ? kNone : (uint16_t)col;
-}
-
-__device__ __forceinline__ bool hash_owner(const Bufs &b, const StepGeom &g, int u, int nslots, int &partner) {
-    const uint64_t H = b.FULL[u];
-    if (H == 0ull) return false;
-    const int h = hash_find(g.HT, g.hmask, H);
-    if (h < 0) {
-        raise_flag(b.CTR, FLAG_BOUNDS);
-        return false;
-    }
-    const uint32_t a = load_u32(&g.HT[h].a), c = load_u32(&g.HT[h].b);
-    if (c == 0u || a == 0u) {
-        raise_flag(b.CTR, FLAG_RUN);
-        return false;
-    }
-    if (a - 1 != (uint32_t)u && c - 1 != (uint32_t)u) {
-        raise_flag(b.CTR, FLAG_RUN);  // more than two splitting edges reached this 2-face
-        return false;
-    }
-    const uint32_t p = (a - 1 == (uint32_t)u) ? c - 1 : a - 1;
-    if (p >= (uint32_t)nslots) {
-        raise_flag(b.CTR, FLAG_BOUNDS);
-        return false;
-    }
-    partner = (int)p;
-    return (uint32_t)u < p;
 }
 
 // One tile of kGemmRows vertex rows x all N <= 256 outputs (see k_gemm). The
@@ -340,7 +332,7 @@ struct GemmLds {
 // split_core: the split of edge e = ab (already read and bounds-checked)
 template <int G, int NC>
 __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int e, int2 ab,
-                                           int lane, int half) {
+                                           int lane, int half, int nslots) {
     const int D = g.D, Wd = g.Wd, ZS = g.ZS;
     // the per-column predicates below (c < N, c vs j, c >= zlo) are cheap to
     // recompute; an empty asm makes their bounds opaque per split so that they
@@ -473,8 +465,14 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     hsum = group_sum<G>(hsum);
     if ((__ballot(bad != 0) >> gshift) & gmask) bad = group_or<G>(bad);
     // ---- stores
-    if (lane < D) b.X[x0 * D + lane] = x0c;
-    if (lane < Wd) b.SG[x0 * Wd + lane] = rx0;
+    {
+        // (the lane's store addresses are rebuilt per split rather than kept
+        // live across the split loop, where they would take more registers)
+        int xl = lane;
+        asm volatile("" : "+v"(xl));
+        if (xl < D) b.X[x0 * D + xl] = x0c;
+        if (xl < Wd) b.SG[x0 * Wd + xl] = rx0;
+    }
     if (lane == 0) {
         if (nz != D - 1 || ktot > g.P) bad |= FLAG_ZERO_COUNT;
         if (bad) raise_flag(b.CTR, bad);
@@ -497,7 +495,8 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
             uint64_t z = kz;
             for (int k = kw == 0 ? kli : (kli >> 1); k > 0; --k) z &= z - 1;
             const int bit = __builtin_ctzll(z);
-            const uint64_t myh = hsum - word_hash(kw, kf) + word_hash(kw, kf | ((minus ? 2ull : 1ull) << bit));
+            // (hkeep drops hash bits only to test the exact pass: collisions on purpose)
+            const uint64_t myh = (hsum - word_hash(kw, kf) + word_hash(kw, kf | ((minus ? 2ull : 1ull) << bit))) & g.hkeep;
             const size_t slot = sbase + lane;
             b.PINFO[slot] = ((uint32_t)kw << 8) | ((uint32_t)bit << 1) | (uint32_t)minus;
             if (g.pair_mode == PAIR_SORT) {
@@ -505,15 +504,13 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
                 const uint32_t k24 = (uint32_t)(myh >> 40);
                 b.K32a[slot] = k24 < 0xFFFFFFu ? k24 : 0xFFFFFEu;
                 b.FULL[slot] = myh;
-            } else {
-                const uint64_t hk = myh | (1ull << 63);  // never 0 (= empty)
-                b.FULL[slot] = hk;
-                hash_insert(g.HT, g.hmask, hk, (uint32_t)slot, b.CTR);
+            } else if (g.hmask != 0u) {  // (0: more key slots than the table names; the exact pass pairs the step)
+                hash_insert(b, g, myh, (uint32_t)slot, nslots);
             }
         }
         for (int rr = ktot + lane; rr < g.P; rr += G) {
+            b.PINFO[sbase + rr] = kNoInfo;
             if (g.pair_mode == PAIR_SORT) b.K32a[sbase + rr] = kSentinel;
-            else b.FULL[sbase + rr] = 0ull;
         }
     }
 }
@@ -525,7 +522,8 @@ __device__ __forceinline__ bool split_edge_ok(int2 ab, int V0) {
 }
 
 template <int G, int NC>
-__device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int lane, int half) {
+__device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int lane, int half,
+                                          int nslots) {
     const int e = b.SPL[s];
     if (!split_entry_ok(b, e, E0)) {
         if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
@@ -536,7 +534,7 @@ __device__ __forceinline__ void split_one(const Bufs &b, const StepGeom &g, int 
         if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
         return;
     }
-    split_core<G, NC>(b, g, V0, E0, s, e, ab, lane, half);
+    split_core<G, NC>(b, g, V0, E0, s, e, ab, lane, half, nslots);
 }
 
 }  // namespace pcx

@@ -58,6 +58,7 @@ struct pcx_complex {
     int2 *EDG = nullptr;
     std::vector<int64_t> steps;
     int64_t total_splits = 0, total_pairs = 0;
+    int exact_steps = 0;          // steps whose pairing the exact pass redid
     uint64_t peak = 0;
     double time_ms = 0.0;
     double ktime[PCX_K_COUNT] = {};

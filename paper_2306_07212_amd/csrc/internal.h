@@ -33,6 +33,10 @@ enum {
     CTR_FLAGS = 3,   // FLAG_* bits; every per-step kernel returns at once while any is set
     CTR_FAIL = 4,    // first step that found the storage too small (FLAG_CAPACITY)
     CTR_SMAX = 5,    // largest split count so far in the layer (shapes the split launches)
+    CTR_PFLAGS = 6,  // pairing failures (FLAG_RUN, FLAG_VERIFY, FLAG_BIGSTEP): the host redoes that
+                     // step's pairing exactly; only a failure of the exact pass is an error
+    CTR_PFAIL = 7,   // first step whose pairing failed (INT_MAX: none); kernels of later steps return
+                     // at once, so the failed step's own split always completes
     CTR_V = 8,       // [2] vertex count at the start of a step
     CTR_E = 10,      // [2] edge count at the start of a step
     CTR_TUSED = 12,  // [2] hash-table entries a step used (cleared by the next step)
@@ -48,14 +52,24 @@ enum : int {
     FLAG_VERIFY = 16,     // equal hashes but different exact 2-face sign-vectors
     FLAG_BOUNDS = 32,     // an index outside the live arrays (internal error; the access is skipped)
     FLAG_CAPACITY = 64,   // a step needs more storage than allocated: nothing written, the host grows and redoes it
+    FLAG_BIGSTEP = 128,   // a step with more 2-face key slots than a table word can name (exact pass instead)
 };
+constexpr int kPairFlags = FLAG_RUN | FLAG_VERIFY | FLAG_BIGSTEP;
 
-// One slot of the 2-face hash table; all-zero = empty. a, b = 1 + the key
-// slots of the first and second splitting edge that reached this 2-face.
-struct HEntry {
-    unsigned long long key;
-    uint32_t a, b;
-};
+// One 64-bit word of the 2-face hash table per splitting 2-face; 0 = empty.
+// The first splitting edge to reach a face claims a word with one CAS that
+// publishes its key and its key slot together: bits 63..24 = 40 bits of the
+// face hash, bits 23..0 = 1 + the key slot. The second arrival finds its
+// partner's slot in the value its own CAS returns.
+constexpr int kSlotBits = 24;
+constexpr uint32_t kMaxHashSlots = (1u << kSlotBits) - 2;  // key slots a step may have on the table path
+constexpr unsigned long long kKeyMask = (1ull << 40) - 1;
+constexpr unsigned long long kSlotMask = (1ull << kSlotBits) - 1;
+// Partner record of a key slot, written by the second arrival at its 2-face
+// (or by the exact pass) for both slots of the pair: high 32 bits = 1 + the
+// step that wrote it, low 32 bits = 1 + the other slot. The pair's owner is
+// its smaller slot.
+constexpr uint32_t kNoInfo = 0xFFFFFFFFu;  // PINFO of an unused key slot
 constexpr int kPairItems = 4;  // hash pairing: chunk granularity of the passes, key slots per thread in the batched kernel
 
 enum { PAIR_HASH = 0, PAIR_SORT = 1 };
@@ -71,12 +85,14 @@ struct StepGeom {
     int zlo;         // first pre-activation column carried to new vertices: 0, or j + 1 in the
                      // last subdivided layer (no later evaluation reads the processed columns)
     int pair_mode;   // PAIR_HASH or PAIR_SORT
-    uint32_t hmask;  // hash table slots - 1 (PAIR_HASH); the per-step kernels derive it from the split count
-    HEntry *HT;      // this step's hash table (PAIR_HASH)
-    HEntry *HTo;     // the previous step's table, cleared by this step's pairing
+    uint32_t hmask;  // hash table words - 1 (PAIR_HASH); the per-step kernels derive it from the split count
+    unsigned long long *HT;   // this step's hash table (PAIR_HASH)
+    unsigned long long *HTo;  // the previous step's table, cleared by this step's pairing
     int step, par;   // global neuron step and its parity (selects the CTR_V / CTR_E / CTR_TUSED slot)
     int nx8;         // 1: first crossings go to NX8 (per-step path); 0: to NXT (batched kernel)
     int Vcap, Ecap, Kcap;  // storage the step may fill (else FLAG_CAPACITY)
+    uint64_t hkeep;  // mask of the 2-face hash bits kept (all; fewer only to test the exact pass)
+    int fbits;       // bits of the exact pass's sort key kept (64; fewer only to test its grouping)
 };
 
 // Log of one neuron step, written by its last kernel: counts at its start, its
@@ -97,9 +113,10 @@ struct Bufs {
     int4 *SPLE;       // [Scap] split list of the per-step path: (edge, its two endpoints, 0)
     int *SPLX;        // [Ecap] per-chunk match lists of the compaction (chunk c at its own edge range)
     uint32_t *K32a, *K32b, *VALa, *VALb;  // [Kcap] radix-sort ping-pong
-    uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot
-    uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus
-    int *PART;        // [Kcap] hash pairing: partner slot of an owner slot, else -1
+    uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot (sort pairing)
+    uint32_t *PINFO;  // [Kcap] perturbed entry of the slot: word << 8 | bit << 1 | minus; kNoInfo if unused
+    uint64_t *PART;   // [Kcap] partner record of each key slot (hash pairing and the exact pass)
+    uint64_t *K64a, *K64b;  // [Kcap] exact pass: 64-bit sort keys (ping-pong; VALa / VALb carry the slots)
     uint32_t *HIST;   // [256 * tiles]
     int *SELCNT;      // [kNextBlocks] per-chunk match counts of the compaction (also the pairing passes)
     int *CTR;         // [CTR_COUNT]
@@ -117,11 +134,13 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
 // first crossing of every edge in the layer (NX8; the edge count comes from
 // CTR_E[par]), and the ordered compaction of the edges that cross the layer's
 // first neuron (the first pass of that step's split list: SPLX, SELCNT)
-void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int par, hipStream_t st);
+// (every per-step kernel takes its global step: it returns at once while a hard
+// failure is flagged or a pairing failure of an earlier step is recorded)
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int par, int step, hipStream_t st);
 // the compaction's second pass alone, after launch_next_all over the same E edges
-void launch_gather(const Bufs &b, int E, int par, hipStream_t st);
+void launch_gather(const Bufs &b, int E, int par, int step, hipStream_t st);
 // splitting edges of neuron `target` from the CTR_E[par] edges: SPL, CTR_S
-void launch_select(const Bufs &b, uint16_t target, int par, int grid, hipStream_t st);
+void launch_select(const Bufs &b, uint16_t target, int par, int step, int grid, hipStream_t st);
 // grids (<= kSelBlocks) of the per-step compaction and hash pairing for an
 // expected edge count / key-slot count: small steps take fewer workgroups
 int select_grid(int64_t edges);
@@ -142,13 +161,24 @@ void launch_move_rows(const Bufs &b, const uint8_t *mark, const int *map, int V,
                       uint64_t *SG2, double *Z2, int2 *E2, int Enew, hipStream_t st);
 // result: *keys / *vals (K32a/VALa or K32b/VALb, by the pass count)
 void launch_sort(const Bufs &b, int n, hipStream_t st, const uint32_t **keys, const uint32_t **vals);
+// the same over 64-bit keys K64a / K64b, all bits (the exact pass)
+void launch_sort64(const Bufs &b, int n, hipStream_t st, const uint64_t **keys, const uint32_t **vals);
 // sort pairing (host-known counts): edges from E1 on, the edge count after the step into CTR_E[par ^ 1]
 void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, const uint32_t *keys,
                  const uint32_t *vals, hipStream_t st);
-// hash pairing: count + ordered emit over the key slots, all counts from the
-// device; the emit also clears the previous step's table (g.HTo), writes the
-// next step's edge count and the step's log entry
+// hash pairing (the split recorded the pairs): a check and count pass over the
+// key slots, then the ordered emit, all counts from the device; the emit also
+// clears the previous step's table (g.HTo), writes the next step's edge count
+// and the step's log entry
 void launch_hash_pair(const Bufs &b, const StepGeom &g, int grid, hipStream_t st);
+// the exact pass of one step's pairing (after a pairing failure): every valid
+// key slot's 2-face sign-vector is rebuilt from its new vertex's row, sorted by
+// a 64-bit hash, and grouped by exact comparison of the rows; the pairs are
+// recorded as the table path records them and emitted by launch_hash_pair
+// with the same grid. It needs K64a/K64b, VALa/VALb and HIST for nslots keys.
+void launch_exact_pair(const Bufs &b, const StepGeom &g, int nslots, int grid, hipStream_t st);
+// fill n 64-bit words with v (a kernel, so that no memset node enters a captured graph)
+void launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 
 // backward (backward.hip)
 template <typename T>

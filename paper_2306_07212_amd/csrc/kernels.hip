@@ -15,6 +15,14 @@
 
 namespace pcx {
 
+// A per-step kernel of global step `step` does nothing while a hard failure is
+// flagged or an earlier step's pairing failed (the host redoes that pairing
+// exactly, then queues the later steps again). A step's own pairing failure
+// does not stop its split, which the exact pass needs whole.
+__device__ __forceinline__ bool step_blocked(const int *ctr, int step) {
+    return ctr[CTR_FLAGS] != 0 || ctr[CTR_PFAIL] < step;
+}
+
 // --------------------------------------------------------- step 0: the box
 
 // 2^D corners (bit j of the corner id picks hi_j) and D 2^(D-1) edges between
@@ -320,9 +328,9 @@ __device__ __forceinline__ void sel_chunk(int E, int &c0, int &c1) {
     c1 = min(E, c0 + per);
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target, int par) {
+__global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target, int par, int step) {
     __shared__ int s_w[kThreads / 64];
-    if (b.CTR[CTR_FLAGS]) return;  // an earlier step failed: the host redoes or reports it
+    if (step_blocked(b.CTR, step)) return;  // an earlier step failed: the host redoes or reports it
     const int E = b.CTR[CTR_E + par];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int c0, c1;
@@ -359,10 +367,10 @@ __global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target,
     if (t == 0) b.SELCNT[blockIdx.x] = run - c0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par) {
+__global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par, int step) {
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_base;
-    if (b.CTR[CTR_FLAGS]) return;
+    if (step_blocked(b.CTR, step)) return;
     const int E = b.CTR[CTR_E + par];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int c0, c1;
@@ -394,9 +402,9 @@ int select_grid(int64_t edges) { return clamp_grid((edges + 2047) / 2048); }
 int pair_grid(int64_t slots) { return clamp_grid((slots + 255) / 256); }
 
 // both kernels chunk the edges by the grid they are launched with: the same one
-void launch_select(const Bufs &b, uint16_t target, int par, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_local, dim3(grid), dim3(kThreads), 0, st, b, target, par);
-    hipLaunchKernelGGL(k_sel_gather, dim3(grid), dim3(kThreads), 0, st, b, par);
+void launch_select(const Bufs &b, uint16_t target, int par, int step, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_local, dim3(grid), dim3(kThreads), 0, st, b, target, par, step);
+    hipLaunchKernelGGL(k_sel_gather, dim3(grid), dim3(kThreads), 0, st, b, par, step);
 }
 
 // ------------------------------------ steps 2-3 at a layer start, per edge
@@ -409,9 +417,9 @@ void launch_select(const Bufs &b, uint16_t target, int par, int grid, hipStream_
 // crossing is the layer's neuron 0, in edge order, to its chunk's range of
 // SPLX: the first pass of that step's compaction (byte 0 stands for both
 // "none" and neuron 0, which no later step looks up).
-__global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, int lw0, int lw1, int par) {
+__global__ __launch_bounds__(kThreads) void k_next_all(Bufs b, int V, int Wd, int lw0, int lw1, int par, int step) {
     __shared__ int s_w[kThreads / 64];
-    if (b.CTR[CTR_FLAGS]) return;
+    if (step_blocked(b.CTR, step)) return;
     const int E = b.CTR[CTR_E + par];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -474,12 +482,12 @@ static int next_blocks(int E) {
     return g < 1 ? 1 : (g > kNextBlocks ? kNextBlocks : g);
 }
 
-void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int par, hipStream_t st) {
-    hipLaunchKernelGGL(k_next_all, dim3(next_blocks(E)), dim3(kThreads), 0, st, b, V, Wd, lw0, lw1, par);
+void launch_next_all(const Bufs &b, int V, int Wd, int lw0, int lw1, int E, int par, int step, hipStream_t st) {
+    hipLaunchKernelGGL(k_next_all, dim3(next_blocks(E)), dim3(kThreads), 0, st, b, V, Wd, lw0, lw1, par, step);
 }
 
-void launch_gather(const Bufs &b, int E, int par, hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_gather, dim3(next_blocks(E)), dim3(kThreads), 0, st, b, par);
+void launch_gather(const Bufs &b, int E, int par, int step, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_gather, dim3(next_blocks(E)), dim3(kThreads), 0, st, b, par, step);
 }
 
 // -------------------------------------------- steps 4-5a: split and keys
@@ -502,7 +510,8 @@ void launch_gather(const Bufs &b, int E, int par, hipStream_t st) {
 // holds column k*G + c; the sign words of the layer are built from the chunk
 // ballots, parked in LDS for the lane that owns each word.
 
-// hash-table slots for n keys: a power of two, load factor <= 1/2
+// hash-table words for n key slots (at most n / 2 faces): a power of two, at
+// least 2n, so the table is at most a quarter full
 __device__ __forceinline__ uint32_t table_size(int n) {
     uint32_t t = 256;
     while (t < 2u * (uint32_t)n) t <<= 1;
@@ -511,7 +520,7 @@ __device__ __forceinline__ uint32_t table_size(int n) {
 
 template <int G, int NC>
 __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
-    if (b.CTR[CTR_FLAGS]) return;
+    if (step_blocked(b.CTR, g.step)) return;
     const int V0 = b.CTR[CTR_V + g.par], E0 = b.CTR[CTR_E + g.par], S = b.CTR[CTR_S];
     // every later kernel of the step writes within these bounds
     if ((int64_t)V0 + S > g.Vcap || (int64_t)E0 + (int64_t)S * g.D > g.Ecap || (int64_t)S * g.P > g.Kcap) {
@@ -521,8 +530,13 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
         }
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) b.CTR[CTR_V + (g.par ^ 1)] = V0 + S;
-    if (g.pair_mode == PAIR_HASH) g.hmask = table_size(S * g.P) - 1u;
+    const int nslots = S * g.P;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.CTR[CTR_V + (g.par ^ 1)] = V0 + S;
+        // more key slots than a table word can name: the exact pass pairs this step
+        if (g.pair_mode == PAIR_HASH && (uint32_t)nslots > kMaxHashSlots) raise_pair_flag(b.CTR, FLAG_BIGSTEP, g.step);
+    }
+    if (g.pair_mode == PAIR_HASH) g.hmask = (uint32_t)nslots <= kMaxHashSlots ? table_size(nslots) - 1u : 0u;
     constexpr int groups = kThreads / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
@@ -534,7 +548,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
             if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
             continue;
         }
-        split_core<G, NC>(b, g, V0, E0, s, q.x, ab, lane, half);
+        split_core<G, NC>(b, g, V0, E0, s, q.x, ab, lane, half, nslots);
     }
 }
 
@@ -566,7 +580,8 @@ void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, 
 // Per pass: tile histograms, an exclusive scan over the tiles of each digit
 // (one workgroup per digit), and a stable scatter that adds the totals of the
 // smaller digits and ranks equal digits inside a tile by wave ballots.
-__global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *__restrict__ keys, int n, int shift,
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_sort_hist(const K *__restrict__ keys, int n, int shift,
                                                          uint32_t *__restrict__ hist, int ntiles) {
     __shared__ uint32_t h[kSortBins];
     const int t = threadIdx.x, tile = blockIdx.x;
@@ -575,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *__restri
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const int idx = tile * kSortTile + i * kThreads + t;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xFF], 1u);
+        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
     hist[(size_t)t * ntiles + tile] = h[t];
@@ -622,9 +637,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_scan(uint32_t *hist, int ntil
     if (t == 0) hist[(size_t)kSortBins * ntiles + d] = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t *__restrict__ kin,
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(const K *__restrict__ kin,
                                                             const uint32_t *__restrict__ vin,
-                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                            K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             int n, int shift, const uint32_t *__restrict__ hist,
                                                             int ntiles) {
     __shared__ uint32_t base[kSortBins];
@@ -654,9 +670,9 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t *__res
     for (int i = 0; i < kSortItems; ++i) {
         const int idx = tile * kSortTile + i * kThreads + t;
         const bool valid = idx < n;
-        const uint32_t k = valid ? kin[idx] : 0u;
+        const K k = valid ? kin[idx] : (K)0;
         const uint32_t v = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
-        const uint32_t d = (k >> shift) & 0xFF;
+        const uint32_t d = (uint32_t)(k >> shift) & 0xFFu;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -684,20 +700,32 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t *__res
     }
 }
 
-void launch_sort(const Bufs &b, int n, hipStream_t st, const uint32_t **keys, const uint32_t **vals) {
-    uint32_t *ka = b.K32a, *kb = b.K32b, *va = b.VALa, *vb = b.VALb;
+// passes of 8 bits over the low 8 * passes key bits; the first pass takes the
+// slot ids as values
+template <typename K>
+static void sort_passes(K *ka, K *kb, uint32_t *va, uint32_t *vb, uint32_t *hist, int n, int passes, hipStream_t st,
+                        const K **keys, const uint32_t **vals) {
     const int ntiles = (n + kSortTile - 1) / kSortTile;
-    for (int pass = 0; n > 0 && pass < kSortPasses; ++pass) {
+    for (int pass = 0; n > 0 && pass < passes; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(kThreads), 0, st, ka, n, shift, b.HIST, ntiles);
-        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kThreads), 0, st, b.HIST, ntiles);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(kThreads), 0, st, ka, pass == 0 ? nullptr : va, kb, vb,
-                           n, shift, b.HIST, ntiles);
-        uint32_t *tk = ka; ka = kb; kb = tk;
+        hipLaunchKernelGGL(k_sort_hist<K>, dim3(ntiles), dim3(kThreads), 0, st, ka, n, shift, hist, ntiles);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kThreads), 0, st, hist, ntiles);
+        hipLaunchKernelGGL(k_sort_scatter<K>, dim3(ntiles), dim3(kThreads), 0, st, ka, pass == 0 ? nullptr : va, kb,
+                           vb, n, shift, hist, ntiles);
+        K *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
     *keys = ka;
     *vals = va;
+}
+
+void launch_sort(const Bufs &b, int n, hipStream_t st, const uint32_t **keys, const uint32_t **vals) {
+    sort_passes<uint32_t>(b.K32a, b.K32b, b.VALa, b.VALb, b.HIST, n, kSortPasses, st, keys, vals);
+}
+
+// all 64 key bits (eight passes): the exact pass's sort
+void launch_sort64(const Bufs &b, int n, hipStream_t st, const uint64_t **keys, const uint32_t **vals) {
+    sort_passes<uint64_t>(b.K64a, b.K64b, b.VALa, b.VALb, b.HIST, n, 8, st, keys, vals);
 }
 
 // ------------------------------------------- step 5c: pair and connect
@@ -728,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, i
             continue;
         }
         if ((len & 1) || len > 32) {
-            raise_flag(b.CTR, FLAG_RUN);
+            raise_pair_flag(b.CTR, FLAG_RUN, g.step);
             continue;
         }
         uint32_t used = 0;
@@ -744,7 +772,7 @@ __global__ __launch_bounds__(kThreads) void k_pair(Bufs b, StepGeom g, int V0, i
             int w = u + 1;
             while (w < len && ((used & (1u << w)) || VS[i + w] >= (uint32_t)nslots || b.FULL[VS[i + w]] != hu)) ++w;
             if (w == len) {
-                raise_flag(b.CTR, FLAG_RUN);
+                raise_pair_flag(b.CTR, FLAG_RUN, g.step);
                 break;
             }
             used |= (1u << u) | (1u << w);
@@ -762,31 +790,32 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, c
 
 // ---------------------------------- step 5c with the hash table
 //
-// Every valid key slot u finds its 2-face entry; the smaller of the two slots
-// owns the pair. Owners are emitted in slot order (chunk counts, then an
-// ordered scatter, as in the compaction), so the edge list is deterministic.
+// The split recorded every pair as it found it (the second arrival at a
+// 2-face). Two passes over the key slots emit the pairs in the order of their
+// owner slots: the first checks every valid slot's record (fresh and mutual)
+// and counts the owners of each workgroup's chunk of slots; the second adds
+// the counts of the chunks before its own and ranks the owners inside the
+// chunk by wave ballots. The edge list is therefore the same on every run and
+// whatever the launch shapes.
 __device__ __forceinline__ void pair_chunk(int n, int &c0, int &c1) {
     const int per = ((n + (int)gridDim.x - 1) / (int)gridDim.x + kPairItems - 1) / kPairItems * kPairItems;
     c0 = min(n, (int)blockIdx.x * per);
     c1 = min(n, c0 + per);
 }
 
-// Pass 1: every key slot finds its 2-face entry once; PART[u] = the partner
-// slot if u owns the pair (the smaller slot), else -1. Per-chunk owner counts.
+// Pass 1: check every valid key slot's partner record, count the owners of
+// each chunk (SELCNT).
 __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g) {
     __shared__ int s_w[kThreads / 64];
-    if (b.CTR[CTR_FLAGS]) return;
+    // this step's split must not have failed its pairing (else the exact pass redoes it)
+    if (b.CTR[CTR_FLAGS] || b.CTR[CTR_PFAIL] <= g.step) return;
     const int S = b.CTR[CTR_S], nslots = S * g.P;
-    g.hmask = table_size(nslots) - 1u;
     int c0, c1;
     pair_chunk(nslots, c0, c1);
     int cnt = 0;
-    // one slot per thread: the table probe is a chain of dependent loads
     for (int u = c0 + (int)threadIdx.x; u < c1; u += kThreads) {
-        int partner = -1;
-        const bool own = hash_owner(b, g, u, nslots, partner);
-        b.PART[u] = own ? partner : -1;
-        cnt += own;
+        int partner;
+        cnt += slot_owner(b, g, u, nslots, partner);
     }
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
@@ -798,24 +827,18 @@ __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g) {
     }
 }
 
-// Pass 2: owners in slot order (chunk offsets from pass 1, ordered scatter
-// inside each chunk) append their intersecting edges.
+// Pass 2: owners in slot order append their intersecting edges.
 __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_base;
-    if (b.CTR[CTR_FLAGS]) return;
+    if (b.CTR[CTR_FLAGS] || b.CTR[CTR_PFAIL] <= g.step) return;
     const int S = b.CTR[CTR_S], nslots = S * g.P;
     const int V0 = b.CTR[CTR_V + g.par], E0 = b.CTR[CTR_E + g.par], E1 = E0 + S;
-    const uint32_t clear_n = (uint32_t)b.CTR[CTR_TUSED + (g.par ^ 1)];
-    HEntry *clear_t = g.HTo;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    // the table of the previous step is no longer read: make it empty again
-    for (uint32_t i = blockIdx.x * kThreads + t; i < clear_n; i += gridDim.x * kThreads) {
-        HEntry z;
-        z.key = 0ull;
-        z.a = 0u;
-        z.b = 0u;
-        clear_t[i] = z;
+    // the previous step's table is no longer read: make it empty for the next step
+    if (g.HTo) {
+        const uint32_t clear_n = (uint32_t)b.CTR[CTR_TUSED + (g.par ^ 1)];
+        for (uint32_t i = blockIdx.x * kThreads + t; i < clear_n; i += gridDim.x * kThreads) g.HTo[i] = 0ull;
     }
     int c0, c1;
     pair_chunk(nslots, c0, c1);
@@ -832,7 +855,7 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
             // the next step's counts, and this step's log entry
             const int En = E1 + x + b.SELCNT[blockIdx.x];
             b.CTR[CTR_E + (g.par ^ 1)] = En;
-            b.CTR[CTR_TUSED + g.par] = (int)table_size(nslots);
+            if (g.HT) b.CTR[CTR_TUSED + g.par] = (uint32_t)nslots <= kMaxHashSlots ? (int)table_size(nslots) : 0;
             if (S > b.CTR[CTR_SMAX]) b.CTR[CTR_SMAX] = S;
             if (b.REC) b.REC[g.step] = StepRec{V0, E0, S, En};
         }
@@ -840,12 +863,13 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     __syncthreads();
     int run = s_base;
     // one slot per thread: an owner's edge is a chain of dependent row loads,
-    // so owners are spread over as many threads as possible rather than queued
-    // behind each other in one thread
+    // so owners are spread over as many threads as possible
     for (int tb = c0; tb < c1; tb += kThreads) {
         const int u = tb + t;
-        const int partner = u < c1 ? b.PART[u] : -1;
-        const uint64_t m = __ballot(partner >= 0);
+        // (pass 1 checked every record: a valid slot's partner is fresh and mutual)
+        const int partner = u < c1 && b.PINFO[u] != kNoInfo ? slot_partner(b, g, u, nslots) : -1;
+        const bool own = partner > u;
+        const uint64_t m = __ballot(own);
         __syncthreads();  // s_w of the previous round has been read
         if (lane == 0) s_w[wave] = __popcll(m);
         __syncthreads();
@@ -856,7 +880,7 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
             if (w < wave) wave_off += ws;
             total += ws;
         }
-        if (partner >= 0) {
+        if (own) {
             const int pos = run + wave_off + __popcll(m & ((1ull << lane) - 1ull));
             emit_pair(b, g, V0, nslots, u, partner, (size_t)E1 + pos, false);
         }
@@ -867,6 +891,111 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
 void launch_hash_pair(const Bufs &b, const StepGeom &g, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_hpair_count, dim3(grid), dim3(kThreads), 0, st, b, g);
     hipLaunchKernelGGL(k_hpair_emit, dim3(grid), dim3(kThreads), 0, st, b, g);
+}
+
+// ------------------------------------- step 5c, the exact pass of a step
+//
+// After a pairing failure (a 2-face word reached three times, a valid slot
+// left without a partner, equal hashes of different faces, or a step too big
+// for the table) the step's pairing is redone without trusting any hash: each
+// valid key slot's 2-face sign-vector is rebuilt from its new vertex's row
+// (entries before the neuron, one zero perturbed: Sec. 4.1), the slots are
+// sorted by a second, independent 64-bit hash of it, and inside each run of
+// equal hashes the slots are grouped by comparing the sign-vectors word by
+// word. Every group must have exactly two slots (Sec. 4.2.2); anything else is
+// a true degeneracy of the input. The pairs are recorded as the table path
+// records them, so the emission (and the edge order) is the same.
+
+__device__ __forceinline__ uint64_t face_word(const uint64_t *R, uint32_t info, int w, int wn, int bn) {
+    uint64_t f = R[w] & lt_mask(w, wn, bn);
+    if (w == (int)(info >> 8)) f |= ((info & 1u) ? 2ull : 1ull) << ((info >> 1) & 63u);
+    return f;
+}
+
+__global__ __launch_bounds__(kThreads) void k_exact_keys(Bufs b, StepGeom g, int nslots) {
+    const int V0 = b.CTR[CTR_V + g.par];
+    for (int u = blockIdx.x * kThreads + threadIdx.x; u < nslots; u += gridDim.x * kThreads) {
+        const uint32_t info = b.PINFO[u];
+        uint64_t k = ~0ull;  // unused slots sort last
+        if (info != kNoInfo) {
+            const uint64_t *R = b.SG + (size_t)(V0 + u / g.P) * g.Wd;
+            uint64_t h = 0x243f6a8885a308d3ull;
+            for (int w = 0; w <= g.wn; ++w) h = mix64(h ^ face_word(R, info, w, g.wn, g.bn)) + (uint64_t)(w + 1);
+            if (g.fbits < 64) h &= (1ull << g.fbits) - 1ull;  // (collisions on purpose: a test of the grouping)
+            k = h == ~0ull ? h - 1 : h;
+        }
+        b.K64a[u] = k;
+        b.VALa[u] = (uint32_t)u;
+    }
+}
+
+__device__ __forceinline__ bool same_face(const Bufs &b, const StepGeom &g, int V0, uint32_t ua, uint32_t ub) {
+    const uint64_t *Ra = b.SG + (size_t)(V0 + ua / g.P) * g.Wd, *Rb = b.SG + (size_t)(V0 + ub / g.P) * g.Wd;
+    const uint32_t ia = b.PINFO[ua], ib = b.PINFO[ub];
+    uint64_t diff = 0;
+    for (int w = 0; w <= g.wn; ++w) diff |= face_word(Ra, ia, w, g.wn, g.bn) ^ face_word(Rb, ib, w, g.wn, g.bn);
+    return diff == 0;
+}
+
+constexpr int kExactRun = 64;  // longest run of equal 64-bit hashes the grouping takes
+
+__global__ __launch_bounds__(kThreads) void k_exact_group(Bufs b, StepGeom g, int nslots,
+                                                           const uint64_t *__restrict__ KS,
+                                                           const uint32_t *__restrict__ VS) {
+    const int V0 = b.CTR[CTR_V + g.par];
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < nslots; i += gridDim.x * kThreads) {
+        const uint64_t k = KS[i];
+        if (k == ~0ull) continue;                  // unused slots (sorted last)
+        if (i > 0 && KS[i - 1] == k) continue;     // not the start of a run
+        int j = i + 1;
+        while (j < nslots && KS[j] == k && j - i <= kExactRun) ++j;
+        const int len = j - i;
+        if (len > kExactRun) {
+            raise_flag(b.CTR, FLAG_RUN);  // more than kExactRun slots on one hash: not generic
+            continue;
+        }
+        uint64_t used = 0;
+        for (int a = 0; a < len; ++a) {
+            if (used >> a & 1ull) continue;
+            const uint32_t ua = VS[i + a];
+            int mate = -1, same = 0;
+            for (int c = a + 1; c < len; ++c) {
+                if (used >> c & 1ull) continue;
+                if (same_face(b, g, V0, ua, VS[i + c])) {
+                    if (mate < 0) mate = c;
+                    ++same;
+                }
+            }
+            if (same != 1) {
+                raise_flag(b.CTR, FLAG_RUN);  // a 2-face not met by exactly two splitting edges
+                break;
+            }
+            used |= (1ull << a) | (1ull << mate);
+            record_pair(b, g, ua, VS[i + mate], nslots);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill64(uint64_t *p, size_t n, uint64_t v) {
+    for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) p[i] = v;
+}
+
+void launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st) {
+    if (n == 0) return;
+    const int grid = (int)std::min<size_t>(4096, (n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_fill64, dim3(grid), dim3(kThreads), 0, st, p, n, v);
+}
+
+void launch_exact_pair(const Bufs &b, const StepGeom &g, int nslots, int grid, hipStream_t st) {
+    if (nslots > 0) {
+        const int kg = std::min(8192, (nslots + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_exact_keys, dim3(kg), dim3(kThreads), 0, st, b, g, nslots);
+        const uint64_t *keys = nullptr;
+        const uint32_t *vals = nullptr;
+        launch_sort64(b, nslots, st, &keys, &vals);
+        hipLaunchKernelGGL(k_exact_group, dim3(kg), dim3(kThreads), 0, st, b, g, nslots, keys, vals);
+    }
+    launch_hash_pair(b, g, grid, st);
 }
 
 }  // namespace pcx

@@ -1,0 +1,116 @@
+"""The exact pass of step 5 (Sec. 4.2.2: each splitting 2-face is met by
+exactly two splitting edges, and pairs are found by comparing sign-vectors).
+
+The hash paths only propose pairs: a 2-face word reached three times, a key
+slot left without a partner, or equal hashes of different faces send the step
+to the exact pass, which regroups the step's key slots by comparing their
+2-face sign-vectors word by word. The test hooks PCX_DEBUG_HASH_BITS and
+PCX_DEBUG_EXACT_BITS keep only a few bits of the hashes, so that collisions
+happen in nearly every step: the complexes must not change (bit-identical to
+the run without collisions, and equal to the oracle)."""
+import numpy as np
+import pytest
+
+from checks import assert_same_complex, unpack_signs
+from paper_2306_07212_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+NETS = [
+    ([2, 8, 8, 1], 1, False),
+    ([2, 24, 24, 24, 1], 31, True),
+    ([3, 12, 12, 1], 32, False),
+    ([3, 20, 20, 1], 33, True),
+    ([4, 7, 7, 1], 34, False),
+    ([2, 70, 40, 1], 35, False),
+]
+
+
+@pytest.fixture(scope="module")
+def pcx():
+    from paper_2306_07212_amd import pcx as P
+    return P
+
+
+def run(pcx, net, incl, pairing="hash"):
+    m = pcx.MLP.from_net(net)
+    box = wl.cube(net.D)
+    cx = pcx.extract(m, box.lo, box.hi, include_output=incl, pairing=pairing)
+    out = cx.copy()
+    info = cx.info()
+    steps = cx.steps()
+    cx.close()
+    m.close()
+    return out, info, steps
+
+
+@pytest.mark.parametrize("widths,seed,incl", NETS)
+def test_collisions_go_through_the_exact_pass(pcx, oracle_lib, monkeypatch, widths, seed, incl):
+    net = wl.he_mlp(widths, seed)
+    ref, info0, steps0 = run(pcx, net, incl)
+    assert info0.exact_steps == 0
+    monkeypatch.setenv("PCX_DEBUG_HASH_BITS", "2")
+    monkeypatch.setenv("PCX_DEBUG_EXACT_BITS", "10")
+    got, info, steps = run(pcx, net, incl)
+    # with 2-bit hashes every face starts its probe at one of 4 words, all with the same key:
+    # a step with more than four faces certainly pairs two different faces on the table
+    busy = int((steps0[:, 3] > 8).sum())
+    print(f"[exact] {widths}: {info.exact_steps} of {len(steps)} steps paired by the exact pass "
+          f"({busy} with more than four pairs)", flush=True)
+    assert info.exact_steps >= busy > 0
+    for a, b in zip(got, ref):
+        assert a.shape == b.shape and np.array_equal(a, b), "the exact pass changed the complex"
+    assert np.array_equal(steps, steps0)
+    # the sort mode's collisions (runs of equal 24-bit keys, equal 64-bit hashes) take the same pass;
+    # with every busy step paired exactly, its edges come in the table path's order
+    gs, infs, _ = run(pcx, net, incl, pairing="sort")
+    assert infs.exact_steps > 0
+    X, SG, Ed = gs
+    box = wl.cube(net.D)
+    r = oracle_lib.extract(net, box.lo, box.hi, include_output=incl)
+    assert_same_complex((X, unpack_signs(SG, widths, incl), Ed), (r.X, r.S, r.edges))
+    X, SG, Ed = got
+    assert_same_complex((X, unpack_signs(SG, widths, incl), Ed), (r.X, r.S, r.edges))
+
+
+def test_batched_collisions_retry_on_the_per_step_path(pcx, monkeypatch):
+    """A pairing failure inside the batched kernel sends that network to the
+    per-step path (whose exact pass tells a collision from a degenerate face):
+    every network still comes out bit-identical to pcx_extract."""
+    nets = wl.batch_nets(24)
+    box = wl.cube(2)
+    refs = [run(pcx, n, False)[0] for n in nets]
+    monkeypatch.setenv("PCX_DEBUG_HASH_BITS", "2")
+    monkeypatch.setenv("PCX_DEBUG_EXACT_BITS", "10")
+    mlps = [pcx.MLP.from_net(n) for n in nets]
+    bt = pcx.Batch(mlps, [(box.lo, box.hi)] * len(nets))
+    st = bt.stats()
+    assert st.degenerate == 0 and st.fallbacks > 0
+    for i in range(len(nets)):
+        for a, b in zip(bt.copy(i), refs[i]):
+            assert a.shape == b.shape and np.array_equal(a, b), f"network {i}"
+    bt.close()
+    for m in mlps:
+        m.close()
+
+
+def test_exact_pass_on_the_large_workload_steps(pcx, monkeypatch):
+    """The 768-neuron network on [-0.05, 0.05]^3 with 12-bit table hashes: the
+    exact pass runs on steps of thousands of key slots and gives the same
+    arrays."""
+    net = wl.plain_large()
+    lo, hi = np.full(3, -0.05), np.full(3, 0.05)
+    m = pcx.MLP.from_net(net)
+    cx = pcx.extract(m, lo, hi)
+    ref = cx.copy()
+    cx.close()
+    monkeypatch.setenv("PCX_DEBUG_HASH_BITS", "12")
+    cx = pcx.extract(m, lo, hi)
+    got = cx.copy()
+    info = cx.info()
+    cx.close()
+    m.close()
+    print(f"[exact] large net: {info.exact_steps} of {info.n_steps} steps paired by the exact pass", flush=True)
+    assert info.exact_steps > 100
+    for a, b in zip(got, ref):
+        assert a.shape == b.shape and np.array_equal(a, b)
