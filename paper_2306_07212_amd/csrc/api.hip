@@ -1117,6 +1117,38 @@ int backward_impl(const pcx_mlp *mlp, const pcx_complex *cx, const double *grad,
     if ((rc = ar.alloc(&p, (size_t)cx->V * ZS * sizeof(T)))) return rc;
     T *gz = (T *)p;
     bwd_init<T>(grad, gx, (size_t)cx->V * D, gz, (size_t)cx->V * ZS, st);
+    // every parent's children in increasing order: one sort of (parent, child, side) records
+    const int Vb = cx->n_steps > 0 ? (int)cx->steps[0] : (int)cx->V;
+    const int nrec = 2 * (int)(cx->V - Vb);
+    Bufs sb{};
+    int *pos = nullptr;
+    double *tt = nullptr;
+    T *gtt = nullptr;
+    const uint64_t *skey = nullptr;
+    if (nrec > 0) {
+        if ((rc = ar.alloc(&p, (size_t)nrec * sizeof(uint64_t)))) return rc;
+        sb.K64a = (uint64_t *)p;
+        if ((rc = ar.alloc(&p, (size_t)nrec * sizeof(uint64_t)))) return rc;
+        sb.K64b = (uint64_t *)p;
+        if ((rc = ar.alloc(&p, (size_t)nrec * sizeof(uint32_t)))) return rc;
+        sb.VALa = (uint32_t *)p;
+        if ((rc = ar.alloc(&p, (size_t)nrec * sizeof(uint32_t)))) return rc;
+        sb.VALb = (uint32_t *)p;
+        if ((rc = ar.alloc(&p, (size_t)kSortBins * ((nrec + kSortTile - 1) / kSortTile + 1) * sizeof(uint32_t))))
+            return rc;
+        sb.HIST = (uint32_t *)p;
+        if ((rc = ar.alloc(&p, (size_t)nrec * sizeof(int)))) return rc;
+        pos = (int *)p;
+        if ((rc = ar.alloc(&p, (size_t)cx->V * sizeof(double)))) return rc;
+        tt = (double *)p;
+        if ((rc = ar.alloc(&p, (size_t)cx->V * sizeof(T)))) return rc;
+        gtt = (T *)p;
+        bwd_records(cx->PQ, Vb, (int)cx->V, sb.K64a, dflag, st);
+        const uint32_t *svals = nullptr;
+        launch_sort64(sb, nrec, st, &skey, &svals);
+        bwd_pos(svals, nrec, pos, st);
+        HIPCHK(hipGetLastError());
+    }
     // layers that were not subdivided do not move any vertex
     for (int l = nsub; l < mlp->L; ++l) {
         HIPCHK(hipMemsetAsync(gW[l], 0, (size_t)mlp->widths[l + 1] * mlp->widths[l] * sizeof(double), st));
@@ -1127,7 +1159,8 @@ int backward_impl(const pcx_mlp *mlp, const pcx_complex *cx, const double *grad,
         const int s0 = cx->layer_step0[l];
         for (int j = N - 1; j >= 0; --j) {
             const int64_t *st4 = &cx->steps[(size_t)(s0 + j) * 4];
-            bwd_step<T>(cx->X, cx->Zl[l], cx->PQ, gx, gz, D, N, ZS, j, (int)st4[0], (int)st4[2], dflag, st);
+            bwd_step<T>(cx->X, cx->Zl[l], cx->PQ, gx, gz, D, N, ZS, j, Vb, (int)st4[0], (int)st4[2], skey, nrec, pos,
+                        tt, gtt, dflag, st);
         }
         HIPCHK(hipGetLastError());
         const int Vs = (int)cx->steps[(size_t)s0 * 4];

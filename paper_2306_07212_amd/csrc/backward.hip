@@ -10,11 +10,16 @@
 //   Z(x0)[c] = Z_p[c] + t (Z_q[c] - Z_p[c])  (c != j),   Z(x0)[j] = 0.
 // Reverse mode walks it back: steps in reverse order (children before their
 // parents), then each layer start. Within one step the new vertices are
-// independent; their contributions to the (older) parents are summed with
-// atomic adds. T is the arithmetic type of the gradients (double, or float
-// for the throughput mode); the recorded values are FP64.
+// independent; each parent then sums the contributions of its children of the
+// step itself, in increasing child order (no atomics: the gradients are the
+// same bits on every run). Every parent's children come from one sort of
+// (parent, child) records per backward call. T is the arithmetic type of the
+// gradients (double, or float for the throughput mode); the recorded values
+// are FP64.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "internal.h"
 
@@ -29,49 +34,100 @@ __global__ __launch_bounds__(kThreads) void k_bwd_init(const double *__restrict_
         gz[i] = (T)0;
 }
 
-// One wave per new vertex of the step; lanes over the layer's columns.
+// Records of the creation graph, one per (new vertex, parent): key = parent
+// << 32 | child << 1 | side (side 0: the child's V+ parent, 1: its V- parent),
+// record index 2 (child - Vb) + side. Sorted, they list each parent's
+// children in increasing order.
+__global__ __launch_bounds__(kThreads) void k_bwd_records(const int2 *__restrict__ PQ, int Vb, int V,
+                                                           uint64_t *__restrict__ keys, int *flag) {
+    for (int x0 = Vb + blockIdx.x * kThreads + threadIdx.x; x0 < V; x0 += gridDim.x * kThreads) {
+        const int2 pq = PQ[x0];
+        if ((unsigned)pq.x >= (unsigned)x0 || (unsigned)pq.y >= (unsigned)x0) atomicOr(flag, 1);
+        const uint64_t c2 = (uint64_t)(uint32_t)x0 << 1;
+        keys[2 * (size_t)(x0 - Vb)] = ((uint64_t)(uint32_t)pq.x << 32) | c2;
+        keys[2 * (size_t)(x0 - Vb) + 1] = ((uint64_t)(uint32_t)pq.y << 32) | c2 | 1u;
+    }
+}
+
+// position of every record in the sorted order
+__global__ __launch_bounds__(kThreads) void k_bwd_pos(const uint32_t *__restrict__ vals, int n, int *__restrict__ pos) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) pos[vals[i]] = i;
+}
+
+// One wave per new vertex of the step: t of its splitting edge and dL/dt,
+// from its coordinates and every carried pre-activation but the current one
+// (lanes over columns, a fixed reduction order).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_step(const double *__restrict__ X, const double *__restrict__ Zs,
-                                                        const int2 *__restrict__ PQ, T *__restrict__ gx,
-                                                        T *__restrict__ gz, int D, int N, int ZS, int j, int V0, int S,
-                                                        int *flag) {
+__global__ __launch_bounds__(kThreads) void k_bwd_child(const double *__restrict__ X, const double *__restrict__ Zs,
+                                                         const int2 *__restrict__ PQ, const T *__restrict__ gx,
+                                                         const T *__restrict__ gz, int D, int N, int ZS, int j, int V0,
+                                                         int S, double *__restrict__ tt, T *__restrict__ gtt) {
     const int lane = threadIdx.x & 63;
     const int wv = (blockIdx.x * kThreads + threadIdx.x) >> 6;
     const int nwv = gridDim.x * (kThreads / 64);
     for (int s = wv; s < S; s += nwv) {
         const int x0 = V0 + s;
         const int2 pq = PQ[x0];
-        if ((unsigned)pq.x >= (unsigned)V0 || (unsigned)pq.y >= (unsigned)V0) {
+        const size_t p = pq.x, q = pq.y;
+        const double zp = Zs[p * ZS + j], zq = Zs[q * ZS + j];
+        const double t = zp / (zp - zq);
+        T gt = 0;
+        for (int d = lane; d < D; d += 64) gt += gx[(size_t)x0 * D + d] * (T)(X[q * D + d] - X[p * D + d]);
+        for (int c = lane; c < N; c += 64) {
+            if (c == j) continue;
+            gt += gz[(size_t)x0 * ZS + c] * (T)(Zs[q * ZS + c] - Zs[p * ZS + c]);
+        }
+        for (int o = 32; o > 0; o >>= 1) gt += __shfl_xor(gt, o, 64);
+        if (lane == 0) {
+            tt[x0] = t;
+            gtt[x0] = gt;
+        }
+    }
+}
+
+// One wave per (new vertex, side) record of the step. The record that comes
+// first among its parent's children of this step sums, in child order, every
+// such child's contribution to the parent:
+//   dL/dx_p += (1 - t) dL/dx0,  dL/dZ_p[c] += (1 - t) dL/dZ0[c]  (c != j),
+//   dL/dz_p += dL/dt * dt/dz_p  with dt/dz_p = -z_q / (z_p - z_q)^2
+// (and with t, dt/dz_q = z_p / (z_p - z_q)^2 for the V- parent q).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_parent(const double *__restrict__ Zs, const int2 *__restrict__ PQ,
+                                                          T *__restrict__ gx, T *__restrict__ gz, int D, int N, int ZS,
+                                                          int j, int Vb, int V0, int S,
+                                                          const uint64_t *__restrict__ skey, int nrec,
+                                                          const int *__restrict__ pos, const double *__restrict__ tt,
+                                                          const T *__restrict__ gtt, int *flag) {
+    const int lane = threadIdx.x & 63;
+    const int wv = (blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const int nwv = gridDim.x * (kThreads / 64);
+    for (int r = wv; r < 2 * S; r += nwv) {
+        const int rec = 2 * (V0 - Vb) + r;
+        const int i = pos[rec];
+        if ((unsigned)i >= (unsigned)nrec) {
             if (lane == 0) atomicOr(flag, 1);
             continue;
         }
-        const size_t p = pq.x, q = pq.y;
-        const double zp = Zs[p * ZS + j], zq = Zs[q * ZS + j];
-        const double den = zp - zq;
-        const double t = zp / den;
-        const T tt = (T)t, omt = (T)(1.0 - t);
-        // dL/dt from the coordinates and from every carried pre-activation but the current one
-        T gt = 0;
-        for (int d = lane; d < D; d += 64) {
-            const T g0 = gx[(size_t)x0 * D + d];
-            gt += g0 * (T)(X[q * D + d] - X[p * D + d]);
-            atomicAdd(&gx[p * D + d], omt * g0);
-            atomicAdd(&gx[q * D + d], tt * g0);
-        }
-        for (int c = lane; c < N; c += 64) {
-            if (c == j) continue;
-            const T g0 = gz[(size_t)x0 * ZS + c];
-            if (g0 == (T)0) continue;
-            gt += g0 * (T)(Zs[q * ZS + c] - Zs[p * ZS + c]);
-            atomicAdd(&gz[p * ZS + c], omt * g0);
-            atomicAdd(&gz[q * ZS + c], tt * g0);
-        }
-        for (int o = 32; o > 0; o >>= 1) gt += __shfl_xor(gt, o, 64);
-        if (lane == 0 && gt != (T)0) {
-            // t = z_p / (z_p - z_q): dt/dz_p = -z_q / den^2, dt/dz_q = z_p / den^2
+        const uint64_t k = skey[i];
+        const uint32_t P = (uint32_t)(k >> 32);
+        // a child of P in this step comes before: it is that one's work
+        if (i > 0 && (uint32_t)(skey[i - 1] >> 32) == P && (int)((uint32_t)skey[i - 1] >> 1) >= V0) continue;
+        for (int e = i; e < nrec; ++e) {
+            const uint64_t ke = skey[e];
+            const int c = (int)((uint32_t)ke >> 1);
+            if ((uint32_t)(ke >> 32) != P || c >= V0 + S) break;
+            const int side = (int)(ke & 1u);
+            const int2 pq = PQ[c];
+            const double zp = Zs[(size_t)pq.x * ZS + j], zq = Zs[(size_t)pq.y * ZS + j];
+            const double t = tt[c], den = zp - zq;
             const double inv = 1.0 / (den * den);
-            atomicAdd(&gz[p * ZS + j], gt * (T)(-zq * inv));
-            atomicAdd(&gz[q * ZS + j], gt * (T)(zp * inv));
+            const T coef = side ? (T)t : (T)(1.0 - t);
+            for (int d = lane; d < D; d += 64) gx[(size_t)P * D + d] += coef * gx[(size_t)c * D + d];
+            for (int col = lane; col < N; col += 64) {
+                if (col == j) continue;
+                gz[(size_t)P * ZS + col] += coef * gz[(size_t)c * ZS + col];
+            }
+            if (lane == 0) gz[(size_t)P * ZS + j] += gtt[c] * (T)(side ? zp * inv : -zq * inv);
         }
     }
 }
@@ -135,13 +191,29 @@ template <typename T>
 void bwd_init(const double *grad, T *gx, size_t n, T *gz, size_t nz, hipStream_t st) {
     hipLaunchKernelGGL(k_bwd_init<T>, dim3(1024), dim3(kThreads), 0, st, grad, gx, n, gz, nz);
 }
+void bwd_records(const int2 *PQ, int Vb, int V, uint64_t *keys, int *flag, hipStream_t st) {
+    if (V <= Vb) return;
+    const int grid = std::min(8192, (V - Vb + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_bwd_records, dim3(grid), dim3(kThreads), 0, st, PQ, Vb, V, keys, flag);
+}
+void bwd_pos(const uint32_t *vals, int n, int *pos, hipStream_t st) {
+    if (n <= 0) return;
+    const int grid = std::min(8192, (n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_bwd_pos, dim3(grid), dim3(kThreads), 0, st, vals, n, pos);
+}
 template <typename T>
-void bwd_step(const double *X, const double *Zs, const int2 *PQ, T *gx, T *gz, int D, int N, int ZS, int j, int V0,
-              int S, int *flag, hipStream_t st) {
+void bwd_step(const double *X, const double *Zs, const int2 *PQ, T *gx, T *gz, int D, int N, int ZS, int j, int Vb,
+              int V0, int S, const uint64_t *skey, int nrec, const int *pos, double *tt, T *gtt, int *flag,
+              hipStream_t st) {
     if (S <= 0) return;
     int grid = (S + 3) / 4;
     grid = grid > 8192 ? 8192 : grid;
-    hipLaunchKernelGGL(k_bwd_step<T>, dim3(grid), dim3(kThreads), 0, st, X, Zs, PQ, gx, gz, D, N, ZS, j, V0, S, flag);
+    hipLaunchKernelGGL(k_bwd_child<T>, dim3(grid), dim3(kThreads), 0, st, X, Zs, PQ, gx, gz, D, N, ZS, j, V0, S, tt,
+                       gtt);
+    grid = (2 * S + 3) / 4;
+    grid = grid > 8192 ? 8192 : grid;
+    hipLaunchKernelGGL(k_bwd_parent<T>, dim3(grid), dim3(kThreads), 0, st, Zs, PQ, gx, gz, D, N, ZS, j, Vb, V0, S, skey,
+                       nrec, pos, tt, gtt, flag);
 }
 template <typename T>
 void bwd_layer(const T *gz, int ZS, const double *hin, int hstride, int relu, int Vs, int N, int K, const double *W,
@@ -161,9 +233,9 @@ void bwd_layer(const T *gz, int ZS, const double *hin, int hstride, int relu, in
 template void bwd_init<double>(const double *, double *, size_t, double *, size_t, hipStream_t);
 template void bwd_init<float>(const double *, float *, size_t, float *, size_t, hipStream_t);
 template void bwd_step<double>(const double *, const double *, const int2 *, double *, double *, int, int, int, int, int,
-                               int, int *, hipStream_t);
+                               int, int, const uint64_t *, int, const int *, double *, double *, int *, hipStream_t);
 template void bwd_step<float>(const double *, const double *, const int2 *, float *, float *, int, int, int, int, int,
-                              int, int *, hipStream_t);
+                              int, int, const uint64_t *, int, const int *, double *, float *, int *, hipStream_t);
 template void bwd_layer<double>(const double *, int, const double *, int, int, int, int, int, const double *, double *,
                                 int, double *, double *, double *, int, hipStream_t);
 template void bwd_layer<float>(const float *, int, const double *, int, int, int, int, int, const double *, double *,

@@ -183,9 +183,15 @@ void launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 // backward (backward.hip)
 template <typename T>
 void bwd_init(const double *grad, T *gx, size_t n, T *gz, size_t nz, hipStream_t st);
+// the creation graph's (parent, child, side) records of the new vertices Vb .. V-1, unsorted
+void bwd_records(const int2 *PQ, int Vb, int V, uint64_t *keys, int *flag, hipStream_t st);
+// pos[vals[i]] = i: where each record sits after the sort
+void bwd_pos(const uint32_t *vals, int n, int *pos, hipStream_t st);
+// one step in reverse: each child's t and dL/dt, then each parent sums its children (in order)
 template <typename T>
-void bwd_step(const double *X, const double *Zs, const int2 *PQ, T *gx, T *gz, int D, int N, int ZS, int j, int V0,
-              int S, int *flag, hipStream_t st);
+void bwd_step(const double *X, const double *Zs, const int2 *PQ, T *gx, T *gz, int D, int N, int ZS, int j, int Vb,
+              int V0, int S, const uint64_t *skey, int nrec, const int *pos, double *tt, T *gtt, int *flag,
+              hipStream_t st);
 template <typename T>
 void bwd_layer(const T *gz, int ZS, const double *hin, int hstride, int relu, int Vs, int N, int K, const double *W,
                double *part, int chunks, double *gW, double *gb, T *gzp, int ZSp, hipStream_t st);

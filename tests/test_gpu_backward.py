@@ -83,3 +83,32 @@ def test_backward_needs_the_tape():
     with pytest.raises(pcx.PcxError) as e:
         pcx.backward(m, cx, 1, [1] * 3, [1] * 3)
     assert e.value.code == pcx.PCX_ERR_INVALID
+
+
+def test_backward_is_deterministic():
+    """Repeated backward passes over the same tape and the same dL/dx give the
+    same gradient bits, in FP64 and in FP32: each parent sums its children's
+    contributions in child order, with no atomic accumulation."""
+    import torch
+    from paper_2306_07212_amd import pcx
+    net = wl.differentiable()
+    box = wl.cube(3)
+    m = pcx.MLP.from_net(net)
+    cx = pcx.extract(m, box.lo, box.hi, include_output=True, record_tape=True)
+    V = cx.info().V
+    dev = torch.device("cuda:0")
+    g = torch.tensor(np.random.default_rng(9).standard_normal((V, 3)), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    for prec in (pcx.PCX_F64, pcx.PCX_F32):
+        runs = []
+        for _ in range(3):
+            gW = [torch.full(w.shape, np.nan, dtype=torch.float64, device=dev) for w in net.W]
+            gb = [torch.full(b.shape, np.nan, dtype=torch.float64, device=dev) for b in net.b]
+            pcx.backward(m, cx, g.data_ptr(), [t.data_ptr() for t in gW], [t.data_ptr() for t in gb], prec, stream)
+            torch.cuda.synchronize()
+            runs.append([t.cpu().numpy() for t in gW + gb])
+        for r in runs[1:]:
+            for a, b in zip(r, runs[0]):
+                assert np.all(np.isfinite(a)) and np.array_equal(a, b), "gradients differ between runs"
+    cx.close()
+    m.close()
