@@ -255,6 +255,28 @@ int pcx_server_stats(pcx_server *s, pcx_server_summary *stats);
 /* Waits for every submitted request, then stops the server's threads. */
 void pcx_server_destroy(pcx_server *s);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture
+ * elsewhere in the process, tight serving loops, harnesses that forbid
+ * hipMalloc): the extraction of pcx_extract, written into caller-allocated
+ * device buffers. Every other array the kernels use comes from a static device
+ * scratch of 256 MiB that each GPU the library runs on holds until the process
+ * ends; no device or pinned memory is allocated and no HIP event or stream is
+ * created. coords: max_vertices * D doubles; signs: max_vertices * Wd words
+ * (packing above); edges: max_edges * 2 int32 (all device memory). On success
+ * *info (host) receives the summary (peak_bytes = scratch bytes used, time_ms =
+ * host wall time) and steps (host, n_steps rows of 4 int64 as in
+ * pcx_complex_steps; may be NULL) the per-step counters; the first V rows of
+ * coords / signs and E rows of edges hold the complex, equal to what
+ * pcx_extract returns (same numbering). Errors: PCX_ERR_CAPACITY when the
+ * complex exceeds max_vertices or max_edges (nothing can grow), or when the
+ * scratch these maxima need exceeds 256 MiB (the message gives the bytes);
+ * PCX_ERR_INVALID for prune, record_tape, sort pairing, more than 32
+ * subdivided layers or 128 sign words. The scratch keeps the last call's
+ * contents: calls that overlap on one GPU race, so callers serialize them. */
+int pcx_extract_into(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, double *coords,
+                     uint64_t *signs, int32_t *edges, int64_t max_vertices, int64_t max_edges, pcx_info *info,
+                     int64_t *steps);
+
 /* Gradient of a loss L(coordinates) with respect to every weight and bias,
  * through the vertex positions (Sec. 5.3: a loss on the extracted complex is
  * optimised through its vertices). cx must come from pcx_extract of the same

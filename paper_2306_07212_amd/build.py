@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcx.so")
-SOURCES = ["kernels.hip", "prune.hip", "cells.hip", "backward.hip", "batch.hip", "api.hip", "batch_api.hip", "server.hip"]
+SOURCES = ["kernels.hip", "prune.hip", "cells.hip", "backward.hip", "batch.hip", "api.hip", "batch_api.hip", "server.hip",
+           "noalloc.hip"]
 
 
 def hipcc() -> str:

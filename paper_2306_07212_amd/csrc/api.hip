@@ -266,8 +266,6 @@ struct Extraction {
     }
 };
 
-int degenerate_message(int flags);
-
 // Pruning (Sec. 5.4.2): the signs of the neurons of the later layers (the
 // output included) at every current vertex, written into their sign words by
 // the evaluation, in chunks of rows through two scratch buffers.
@@ -339,6 +337,9 @@ int prune_now(Extraction &x, int64_t &V, int64_t &E, int lwf, int par) {
     return PCX_OK;
 }
 
+}  // namespace
+
+namespace pcx {
 int degenerate_message(int flags) {
     std::string m = "input is not generic:";
     if (flags & FLAG_ZERO_SIGN) m += " a vertex lies on a hyperplane;";
@@ -349,8 +350,7 @@ int degenerate_message(int flags) {
     if (flags & FLAG_BOUNDS) return fail(PCX_ERR_DEVICE, "internal error: a kernel saw an index out of range");
     return fail(PCX_ERR_DEGENERATE, m);
 }
-
-}  // namespace
+}  // namespace pcx
 
 extern "C" {
 

@@ -20,6 +20,9 @@
 namespace pcx {
 // Records msg as the calling thread's last error and returns code.
 int fail(int code, const std::string &msg);
+// The error for device failure flags (FLAG_*): PCX_ERR_DEGENERATE with what
+// was found, or PCX_ERR_DEVICE for an internal index error.
+int degenerate_message(int flags);
 
 // Predicted vertex count of the complex of a random-initialised network with N
 // subdivided neurons on a box in R^D: 0.6 N^D / ((D-1)! 2^(D-2)) (fitted on

@@ -15,6 +15,15 @@ from typing import Optional, Sequence
 
 import numpy as np
 
+# PyTorch (device memory and streams for the callers of this library) ships its
+# own HIP runtime under the same soname as ROCm's. Whichever loads first serves
+# the whole process, and PyTorch cannot start on another build's runtime: so
+# torch, when installed, is loaded before libpcx.so, and both share its runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcx.so")
 
@@ -31,7 +40,7 @@ SYMBOLS = [
     "pcx_complex_free", "pcx_cache_trim", "pcx_complex_copy_device", "pcx_backward",
     "pcx_extract_batch", "pcx_batch_info", "pcx_batch_copy", "pcx_batch_summary", "pcx_batch_free",
     "pcx_batch_tune", "pcx_server_create", "pcx_server_submit", "pcx_server_poll", "pcx_server_wait",
-    "pcx_server_copy", "pcx_server_release", "pcx_server_stats", "pcx_server_destroy",
+    "pcx_server_copy", "pcx_server_release", "pcx_server_stats", "pcx_server_destroy", "pcx_extract_into",
 ]
 PCX_F64, PCX_F32 = 0, 1
 
@@ -120,6 +129,7 @@ def _load():
     lib.pcx_server_stats.argtypes = [vp, C.POINTER(_ServerSummary)]
     lib.pcx_server_destroy.argtypes = [vp]
     lib.pcx_server_destroy.restype = None
+    lib.pcx_extract_into.argtypes = [vp, PD, PD, C.POINTER(_Opts), vp, vp, vp, i64, i64, C.POINTER(_Info), vp]
     lib.pcx_cache_trim.argtypes = []
     lib.pcx_cache_trim.restype = None
     for s in SYMBOLS:
@@ -333,6 +343,29 @@ def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=Non
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))
     return Complex(h, mlp.widths, include_output)
+
+
+def extract_into(mlp: MLP, lo, hi, coords_ptr: int, signs_ptr: int, edges_ptr: int, max_vertices: int,
+                 max_edges: int, include_output: bool = False, stream=None):
+    """``pcx_extract_into``: the extraction written into caller-allocated device
+    buffers (raw pointers), with no device allocation by the library. Returns
+    (Info, per-step counters [n_steps, 4] int64)."""
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
+        raise ValueError("lo and hi must have D entries")
+    o = _Opts(int(bool(include_output)), 0, 0, 0, 0, stream, 0, 0)
+    L = len(mlp.widths) - 1
+    n_steps = sum(mlp.widths[1:L + 1 if include_output else L])
+    steps = np.zeros((max(1, n_steps), 4), np.int64)
+    i = _Info()
+    PD = C.POINTER(C.c_double)
+    _check(_lib.pcx_extract_into(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), coords_ptr,
+                                 signs_ptr, edges_ptr, int(max_vertices), int(max_edges), C.byref(i),
+                                 steps.ctypes.data))
+    info = Info(i.V, i.E, i.D, i.M, i.Wd, i.n_steps, i.total_splits, i.total_pairs, i.peak_bytes, i.time_ms,
+                i.exact_steps)
+    return info, steps[:n_steps]
 
 
 def extract_simplex(mlp: MLP, corners, include_output: bool = False, timing=0, stream=None, max_bytes: int = 0,
