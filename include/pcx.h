@@ -90,7 +90,8 @@ typedef struct {
     int32_t exact_steps;    /* steps whose 2-face pairing was redone by the exact pass (a hash
                                collision, or a step with more than 2^24 - 2 key slots); the result
                                is the same complex either way */
-    int32_t reserved;
+    int32_t from_graph;     /* 1: a repeat of the network's last extraction (same box and options),
+                               replayed from its captured HIP graph (the same complex) */
 } pcx_info;
 
 const char *pcx_last_error(void);
@@ -105,7 +106,13 @@ void pcx_mlp_free(pcx_mlp *mlp);
 /* Edge subdivision of the box [lo, hi] (D host doubles each, lo < hi) by every
  * subdivided neuron of mlp, in layer order (Sec. 4.2). On success *out owns
  * the complex on the device. On error *out is NULL. Work is queued on
- * opts->stream; the call returns when the complex is complete. */
+ * opts->stream; the call returns when the complex is complete. A network keeps
+ * the step log of its last extraction (hash pairing, no prune, tape, timing or
+ * byte cap); its third request with the same box and options captures the
+ * whole kernel sequence in a HIP graph (storage of its own, up to 512 MiB per
+ * network and 4 GiB over all networks, held until pcx_mlp_free) and later ones
+ * replay it (PCX_NO_GRAPH=1 in the environment turns this off). A replay whose
+ * steps differ from the log is discarded and the ordinary path runs. */
 int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts,
                 pcx_complex **out);
 

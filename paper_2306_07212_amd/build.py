@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcx.so")
 SOURCES = ["kernels.hip", "prune.hip", "cells.hip", "backward.hip", "batch.hip", "api.hip", "batch_api.hip", "server.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "graph.hip"]
 
 
 def hipcc() -> str:

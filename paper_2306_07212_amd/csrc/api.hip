@@ -18,6 +18,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "host.h"
 
 namespace pcx {
@@ -64,6 +65,35 @@ struct EventPool {
     }
 };
 
+// Pinned counter buffers and events of one thread on one device, kept for the
+// thread's later extractions: creating them costs more than a small
+// extraction does. (Never released: the runtime may be gone at thread exit.)
+struct HostRes {
+    int *pinned = nullptr;  // [3][CTR_COUNT]: counters after a drain, two snapshots
+    hipEvent_t snap[2] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+    hipStream_t cap = nullptr;  // stream on which graphs are captured
+    bool busy = false;
+};
+
+int host_res(HostRes *&out) {
+    thread_local std::unordered_map<int, HostRes *> *per_dev = new std::unordered_map<int, HostRes *>();
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HostRes *&r = (*per_dev)[dev];
+    if (!r) {
+        auto *n = new HostRes();
+        HIPCHK(hipHostMalloc((void **)&n->pinned, 3 * CTR_COUNT * sizeof(int), hipHostMallocDefault));
+        for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&n->snap[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreate(&n->t0));
+        HIPCHK(hipEventCreate(&n->t1));
+        HIPCHK(hipStreamCreateWithFlags(&n->cap, hipStreamNonBlocking));
+        r = n;
+    }
+    if (r->busy) return fail(PCX_ERR_DEVICE, "internal error: nested extraction on one thread");
+    out = r;
+    return PCX_OK;
+}
+
 struct Extraction {
     const pcx_mlp *mlp;
     hipStream_t st;
@@ -87,12 +117,21 @@ struct Extraction {
     double ktime[PCX_K_COUNT] = {};
     int64_t klaunch[PCX_K_COUNT] = {};
 
+    HostRes *res = nullptr;  // borrowed: the thread's pinned counters and events
+
     ~Extraction() {
-        if (hctr) (void)hipHostFree(hctr);
-        for (int i = 0; i < 2; ++i) {
-            if (hsnap[i]) (void)hipHostFree(hsnap[i]);
-            if (evsnap[i]) (void)hipEventDestroy(evsnap[i]);
-        }
+        if (res) res->busy = false;
+    }
+    int attach_host() {
+        int rc;
+        if ((rc = host_res(res))) return rc;
+        res->busy = true;
+        hctr = res->pinned;
+        hsnap[0] = res->pinned + CTR_COUNT;
+        hsnap[1] = res->pinned + 2 * CTR_COUNT;
+        evsnap[0] = res->snap[0];
+        evsnap[1] = res->snap[1];
+        return PCX_OK;
     }
 
     // every enqueued kernel done; hctr = the device counters
@@ -365,6 +404,7 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
         if (widths[l] < 1) return fail(PCX_ERR_INVALID, "every width must be >= 1");
     if (widths[0] > 16) return fail(PCX_ERR_INVALID, "input dimension D must be 1..16");
     pcx_mlp *m = new pcx_mlp();
+    m->gcache = graph_cache_new();
     m->L = n_layers;
     m->D = widths[0];
     m->widths.assign(widths, widths + n_layers + 1);
@@ -408,6 +448,7 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
 
 void pcx_mlp_free(pcx_mlp *m) {
     if (!m) return;
+    graph_cache_free(m->gcache);
     for (auto p : m->Wt) (void)hipFree(p);
     for (auto p : m->Wr) (void)hipFree(p);
     for (auto p : m->b) (void)hipFree(p);
@@ -429,11 +470,31 @@ struct Domain {
     std::vector<int2> E0;                       // [ne]
 };
 
-int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pcx_complex **out) {
+// Small networks (predicted complex of at most kTinyVertices vertices) go to
+// the batched kernel as a batch of one: one launch instead of several per
+// neuron step, the same complex (PCX_NO_TINY=1 in the environment turns it off).
+constexpr double kTinyVertices = 1024.0;
+bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
+    const char *off = getenv("PCX_NO_TINY");
+    if (off && off[0] == '1') return false;
+    if (o.pairing != PCX_PAIR_HASH || o.prune || o.record_tape || o.timing || o.max_bytes) return false;
+    if (mlp->D > kBatchMaxD || mlp->L > kBatchMaxLayers) return false;
+    int N = 0, Wd = 1;
+    for (int l = 1; l <= nsub; ++l) {
+        if (mlp->widths[l] > kMaxWidth) return false;
+        N += mlp->widths[l];
+        Wd += (mlp->widths[l] + 31) / 32;
+    }
+    return Wd <= kBatchMaxWords && N > 0 && predict_vertices(mlp->D, N) <= kTinyVertices;
+}
+
+int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pcx_complex **out,
+                 bool tiny_ok = false) {
     pcx_opts o{};
     if (opts) o = *opts;
     const int D = mlp->D, L = mlp->L;
     const int nsub = o.include_output ? L : L - 1;
+    if (tiny_ok && dom.lo && tiny_eligible(mlp, o, nsub)) return tiny_extract(mlp, dom.lo, dom.hi, o, out);
     std::vector<int> lw(nsub + 1);
     lw[0] = 1;
     int M = dom.m, ZS = 1, n_steps = 0;
@@ -475,10 +536,11 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
 
     const bool box = dom.lo != nullptr;
     const size_t V0 = box ? (size_t)1 << D : dom.W0.size(), E0 = box ? (size_t)D << (D - 1) : dom.E0.size();
-    HIPCHK(hipHostMalloc((void **)&x.hctr, CTR_COUNT * sizeof(int), hipHostMallocDefault));
-    for (int i = 0; i < 2; ++i) {
-        HIPCHK(hipHostMalloc((void **)&x.hsnap[i], CTR_COUNT * sizeof(int), hipHostMallocDefault));
-        HIPCHK(hipEventCreateWithFlags(&x.evsnap[i], hipEventDisableTiming));
+    if ((rc = x.attach_host())) return rc;
+    if (dom.lo) {
+        // a repeat of the network's last extraction: its captured graph
+        rc = graph_try(mlp, dom.lo, dom.hi, o, st, x.res->cap, x.res->t0, x.res->t1, x.res->pinned, out);
+        if (rc != kGraphDeclined) return rc;
     }
     {
         void *p;
@@ -545,16 +607,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         HIPCHK(hipMemcpyAsync(x.b.CTR, x.hctr, sizeof h, hipMemcpyHostToDevice, st));
     }
 
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } evg{t0, t1};
+    hipEvent_t t0 = x.res->t0, t1 = x.res->t1;
     HIPCHK(hipEventRecord(t0, st));
     std::vector<uint64_t> rows0;
     if (box) {
@@ -966,11 +1019,23 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     m->hintV.store(std::max<int64_t>(m->hintV.load(), V));
     m->hintE.store(std::max<int64_t>(m->hintE.load(), Ebound));
     m->hintS.store(std::max<int64_t>(m->hintS.load(), Smax));
+    if (dom.lo) graph_record(mlp, dom.lo, dom.hi, o, cx, Ebound, Smax);
     *out = cx;
     return PCX_OK;
 }
 
 }  // namespace
+
+namespace pcx {
+int extract_ordinary(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out) {
+    Domain dom;
+    dom.m = 2 * mlp->D;
+    dom.lo = lo;
+    dom.hi = hi;
+    return extract_impl(mlp, dom, opts, out, false);
+}
+
+}  // namespace pcx
 
 extern "C" {
 
@@ -984,7 +1049,7 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     dom.m = 2 * mlp->D;
     dom.lo = lo;
     dom.hi = hi;
-    return extract_impl(mlp, dom, opts, out);
+    return extract_impl(mlp, dom, opts, out, true);
 }
 
 int pcx_extract_simplex(const pcx_mlp *mlp, const double *corners, const pcx_opts *opts, pcx_complex **out) {
@@ -1043,6 +1108,7 @@ int pcx_complex_info(const pcx_complex *cx, pcx_info *info) {
     info->peak_bytes = cx->peak;
     info->time_ms = cx->time_ms;
     info->exact_steps = cx->exact_steps;
+    info->from_graph = cx->from_graph;
     return PCX_OK;
 }
 

@@ -22,6 +22,7 @@ struct BatchNet {
     int widths[kBatchMaxLayers + 1];
     int L, nsub, D;
     double lo[kBatchMaxD], hi[kBatchMaxD];
+    StepRec *rec;  // per-step log of this network (null: not kept)
 };
 
 struct BatchResult {

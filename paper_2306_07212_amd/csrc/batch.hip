@@ -199,7 +199,10 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
         }
         for (int j = 0; j < N; ++j, ++step) {
             const int S = block_select(b, E, (uint16_t)j, s_w);
-            if (S == 0) continue;
+            if (S == 0) {
+                if (t == 0 && net.rec) net.rec[step] = StepRec{V, E, 0, E};
+                continue;
+            }
             uint32_t tsz = 256;
             while (tsz < 2u * (uint32_t)(S * P)) tsz <<= 1;
             if (V + S > Vcap || E + S * D > Ecap || S * P > Kcap || tsz > A.tcap) {
@@ -239,6 +242,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             int np = 0;
             if (P > 0) np = block_pair(b, g, V, E + S, S * P, s_w);
+            if (t == 0 && net.rec) net.rec[step] = StepRec{V, E, S, E + S + np};
             V += S;
             E += S + np;
             splits += S;

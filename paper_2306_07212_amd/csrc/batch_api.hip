@@ -21,6 +21,9 @@ struct pcx_batch {
     int2 *oE = nullptr;
     double time_ms = 0.0, kernel_ms = 0.0;
     int workgroups = 0, wg_per_cu = 0, n_fallback = 0;
+    std::vector<std::vector<int64_t>> steps;  // per-step counters of each batched network (when kept)
+    std::vector<int> nsub, ZS;
+    std::vector<std::vector<uint64_t>> valid;
 };
 
 namespace {
@@ -30,10 +33,12 @@ std::map<std::vector<int>, int> g_tuned;  // batch signature -> workgroups per C
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
-                      const pcx_opts *opts, pcx_batch **out) {
+// The batched extraction; with keep_steps, every batched network's per-step
+// counters are logged too (the batch of one behind small pcx_extract calls).
+int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi, const pcx_opts *opts,
+              bool keep_steps, pcx_batch **out) {
     if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (n < 0 || (n > 0 && (!mlps || !lo || !hi))) return fail(PCX_ERR_INVALID, "NULL argument");
@@ -50,6 +55,10 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
     bt->Wd.resize(n);
     bt->M.resize(n);
     bt->nsteps.resize(n);
+    bt->nsub.resize(n);
+    bt->ZS.resize(n);
+    bt->valid.resize(n);
+    bt->steps.resize(n);
     std::vector<BatchNet> nets(n);
     std::vector<double> pred(n);
     std::vector<int> batched, direct;
@@ -82,6 +91,18 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
         bt->Wd[i] = Wd;
         bt->M[i] = M;
         bt->nsteps[i] = N;
+        bt->nsub[i] = nsub;
+        bt->ZS[i] = ZS;
+        if (keep_steps) {
+            std::vector<uint64_t> v(Wd, 0);
+            for (int e = 0; e < 2 * D; ++e) v[0] |= 1ull << (2 * e);
+            int w0 = 1;
+            for (int l = 1; l <= nsub; ++l) {
+                for (int c = 0; c < m->widths[l]; ++c) v[w0 + (c >> 5)] |= 1ull << (2 * (c & 31));
+                w0 += (m->widths[l] + 31) / 32;
+            }
+            bt->valid[i] = v;
+        }
         pred[i] = predict_vertices(D, N);
         if (pred[i] > 65536.0) fits = false;  // larger networks use the per-step path
         if (fits) {
@@ -117,6 +138,9 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
     Arena ar;
     ar.cap = o.max_bytes;
     float kms = 0.f;
+    StepRec *rec_dev = nullptr;
+    size_t rec_tot = 0;
+    std::vector<size_t> rec_off(n, 0);
     if (!batched.empty()) {
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
@@ -176,6 +200,19 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
         A.ticket = (int *)(A.pool + 4);
         if ((rc = ar.alloc(&p, (size_t)n * sizeof(BatchResult)))) goto fail_out;
         A.res = (BatchResult *)p;
+        if (keep_steps) {
+            size_t tot = 0;
+            for (int i : batched) tot += (size_t)bt->nsteps[i];
+            if ((rc = ar.alloc(&p, std::max<size_t>(tot, 1) * sizeof(StepRec)))) goto fail_out;
+            rec_dev = (StepRec *)p;
+            size_t off = 0;
+            for (int i : batched) {
+                nets[i].rec = rec_dev + off;
+                rec_off[i] = off;
+                off += (size_t)bt->nsteps[i];
+            }
+            rec_tot = tot;
+        }
         A.n = (int)batched.size();
         A.arena_bytes = abytes;
         A.vbytes = vbytes;
@@ -206,7 +243,21 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
             HIPCHK(hipGetLastError());
             HIPCHK(hipEventRecord(e1, st));
             HIPCHK(hipMemcpyAsync(bt->res.data(), A.res, (size_t)n * sizeof(BatchResult), hipMemcpyDeviceToHost, st));
+            std::vector<StepRec> rec(rec_tot);
+            if (rec_tot) HIPCHK(hipMemcpyAsync(rec.data(), rec_dev, rec_tot * sizeof(StepRec), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
+            for (int i : batched) {
+                if (!keep_steps || bt->res[i].status != BATCH_OK) continue;
+                auto &sv = bt->steps[i];
+                sv.resize((size_t)bt->nsteps[i] * 4);
+                for (int k = 0; k < bt->nsteps[i]; ++k) {
+                    const StepRec &q = rec[rec_off[i] + k];
+                    sv[(size_t)k * 4 + 0] = q.V0;
+                    sv[(size_t)k * 4 + 1] = q.E0;
+                    sv[(size_t)k * 4 + 2] = q.S;
+                    sv[(size_t)k * 4 + 3] = 2 * ((int64_t)q.E1 - q.E0 - q.S);
+                }
+            }
             HIPCHK(hipEventElapsedTime(&kms, e0, e1));
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
@@ -234,7 +285,7 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
         pcx_opts od = o;
         for (int i : direct) {
             pcx_complex *cx = nullptr;
-            int r = pcx_extract(mlps[i], lo + offs[i], hi + offs[i], &od, &cx);
+            int r = extract_ordinary(mlps[i], lo + offs[i], hi + offs[i], &od, &cx);
             BatchResult &br = bt->res[i];
             std::memset(&br, 0, sizeof br);
             if (r == PCX_ERR_DEGENERATE) {
@@ -262,6 +313,66 @@ fail_out:
     pcx_batch_free(bt);
     return rc;
 }
+
+}  // namespace
+
+extern "C" int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
+                                 const pcx_opts *opts, pcx_batch **out) {
+    return batch_run(n, mlps, lo, hi, opts, false, out);
+}
+
+namespace pcx {
+
+// A small network's pcx_extract as a batch of one: one launch of the batched
+// kernel (one workgroup runs every step) instead of several launches per
+// neuron step. The complex, its numbering and its per-step counters are those
+// of the per-step path (the same device functions in the same order).
+int tiny_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts &o, pcx_complex **out) {
+    *out = nullptr;
+    pcx_batch *bt = nullptr;
+    const pcx_mlp *const one[1] = {mlp};
+    int rc = batch_run(1, one, lo, hi, &o, true, &bt);
+    if (rc) return rc;
+    const BatchResult &r = bt->res[0];
+    if (r.status == BATCH_DEGENERATE) {
+        pcx_batch_free(bt);
+        return fail(PCX_ERR_DEGENERATE, "input is not generic");
+    }
+    if (bt->fallback[0]) {  // too large for the kernel's arena: the per-step path ran
+        *out = bt->fallback[0];
+        bt->fallback[0] = nullptr;
+        pcx_batch_free(bt);
+        return PCX_OK;
+    }
+    auto *cx = new pcx_complex();
+    cx->D = bt->D[0];
+    cx->M = bt->M[0];
+    cx->Wd = bt->Wd[0];
+    cx->n_steps = bt->nsteps[0];
+    cx->V = r.V;
+    cx->E = r.E;
+    cx->valid = bt->valid[0];
+    // the output pools hold this network alone, from offset 0: they become its arrays
+    cx->X = bt->oX;
+    cx->SG = bt->oSG;
+    cx->EDG = bt->oE;
+    bt->oX = nullptr;
+    bt->oSG = nullptr;
+    bt->oE = nullptr;
+    cx->steps = bt->steps[0];
+    cx->total_splits = r.splits;
+    cx->total_pairs = r.pairs;
+    cx->time_ms = bt->kernel_ms;
+    cx->ZS = bt->ZS[0];
+    cx->nsub = bt->nsub[0];
+    pcx_batch_free(bt);
+    *out = cx;
+    return PCX_OK;
+}
+
+}  // namespace pcx
+
+extern "C" {
 
 int pcx_batch_info(const pcx_batch *bt, int32_t i, pcx_info *info) {
     if (!bt || !info || i < 0 || i >= bt->n) return fail(PCX_ERR_INVALID, "bad argument");

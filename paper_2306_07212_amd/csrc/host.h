@@ -42,6 +42,12 @@ inline double predict_vertices(int D, int N) {
         if (e_ != hipSuccess) return pcx::fail(PCX_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+namespace pcx {
+struct GraphCache;
+GraphCache *graph_cache_new();
+void graph_cache_free(GraphCache *c);
+}  // namespace pcx
+
 struct pcx_mlp {
     int L = 0, D = 0;
     std::vector<int> widths;
@@ -49,6 +55,7 @@ struct pcx_mlp {
     std::vector<double *> Wr;  // device, layer l: [N_l][N_{l-1}] as given (backward pass)
     std::vector<double *> b;   // device, [N_l]
     std::atomic<int64_t> hintV{0}, hintE{0}, hintS{0};  // sizes seen by earlier extractions (capacity hints)
+    pcx::GraphCache *gcache = nullptr;  // the last extraction's step log and its captured graph (graph.hip)
 };
 
 struct pcx_complex {
@@ -62,6 +69,7 @@ struct pcx_complex {
     std::vector<int64_t> steps;
     int64_t total_splits = 0, total_pairs = 0;
     int exact_steps = 0;          // steps whose pairing the exact pass redid
+    int from_graph = 0;           // 1: replayed from the network's captured graph
     uint64_t peak = 0;
     double time_ms = 0.0;
     double ktime[PCX_K_COUNT] = {};
@@ -192,4 +200,18 @@ struct Arena {
     }
 };
 
+// Repeated extractions as a replayed graph (graph.hip). graph_try serves the
+// extraction from the network's cached graph when its step log matches the
+// request (same box and options), building the graph on first use; it returns
+// kGraphDeclined when the ordinary path must run. graph_record keeps the step
+// log of a finished ordinary extraction for the next request.
+constexpr int kGraphDeclined = 1000;
+// pcx_extract without the batch-of-one path for small networks (what a batch's
+// own fallback runs), and that path (batch_api.hip)
+int extract_ordinary(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out);
+int tiny_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts &o, pcx_complex **out);
+int graph_try(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts &o, hipStream_t st,
+              hipStream_t cs, hipEvent_t t0, hipEvent_t t1, int *pinned, pcx_complex **out);
+void graph_record(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts &o, const pcx_complex *cx,
+                  int64_t Ebound, int64_t Smax);
 }  // namespace pcx

@@ -179,6 +179,8 @@ void launch_hash_pair(const Bufs &b, const StepGeom &g, int grid, hipStream_t st
 void launch_exact_pair(const Bufs &b, const StepGeom &g, int nslots, int grid, hipStream_t st);
 // fill n 64-bit words with v (a kernel, so that no memset node enters a captured graph)
 void launch_fill64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
+// the device counters at the start of an extraction from V0 vertices and E0 edges
+void launch_ctr_init(int *ctr, int V0, int E0, hipStream_t st);
 
 // backward (backward.hip)
 template <typename T>

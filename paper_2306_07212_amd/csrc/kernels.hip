@@ -561,7 +561,20 @@ int split_blocks(int S_hint, int Nl) {
     return grid < 1 ? 1 : (grid > 16384 ? 16384 : grid);
 }
 
+template <int NC>
+static void launch_split_plain(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_split<32, NC>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+}
+
 void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+    if (!t0 && !t1) {
+        // untimed: the plain launch (also what a captured graph records)
+        if (g.Nl <= 32) launch_split_plain<1>(b, g, blocks, st);
+        else if (g.Nl <= 64) launch_split_plain<2>(b, g, blocks, st);
+        else if (g.Nl <= 128) launch_split_plain<4>(b, g, blocks, st);
+        else launch_split_plain<8>(b, g, blocks, st);
+        return;
+    }
     if (g.Nl <= 32)
         hipExtLaunchKernelGGL((k_split<32, 1>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else if (g.Nl <= 64)
@@ -974,6 +987,17 @@ __global__ __launch_bounds__(kThreads) void k_exact_group(Bufs b, StepGeom g, in
             record_pair(b, g, ua, VS[i + mate], nslots);
         }
     }
+}
+
+// the counters at the start of an extraction (a kernel, so that a captured graph can set them)
+__global__ void k_ctr_init(int *ctr, int V0, int E0) {
+    const int i = threadIdx.x;
+    if (i < CTR_COUNT)
+        ctr[i] = i == CTR_V ? V0 : i == CTR_E ? E0 : (i == CTR_FAIL || i == CTR_PFAIL) ? 0x7fffffff : 0;
+}
+
+void launch_ctr_init(int *ctr, int V0, int E0, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctr_init, dim3(1), dim3(64), 0, st, ctr, V0, E0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill64(uint64_t *p, size_t n, uint64_t v) {

@@ -67,7 +67,7 @@ class _Info(C.Structure):
     _fields_ = [("V", C.c_int64), ("E", C.c_int64), ("D", C.c_int32), ("M", C.c_int32), ("Wd", C.c_int32),
                 ("n_steps", C.c_int32), ("total_splits", C.c_int64), ("total_pairs", C.c_int64),
                 ("peak_bytes", C.c_uint64), ("time_ms", C.c_double), ("exact_steps", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("from_graph", C.c_int32)]
 
 
 class _ServerOpts(C.Structure):
@@ -207,6 +207,7 @@ class Info:
     peak_bytes: int
     time_ms: float
     exact_steps: int = 0
+    from_graph: int = 0
 
 
 def sign_layout(widths: Sequence[int], include_output: bool = False, m: Optional[int] = None):
@@ -241,7 +242,7 @@ class Complex:
         i = _Info()
         _check(_lib.pcx_complex_info(self._h, C.byref(i)))
         return Info(i.V, i.E, i.D, i.M, i.Wd, i.n_steps, i.total_splits, i.total_pairs, i.peak_bytes, i.time_ms,
-                    i.exact_steps)
+                    i.exact_steps, i.from_graph)
 
     def steps(self) -> np.ndarray:
         n = self.info().n_steps

@@ -67,9 +67,37 @@ def test_plain_small_matches_oracle_and_golden(oracle_lib, pcx):
     ([2, 1, 1, 1], 109, False),       # width-1 layers
 ])
 @pytest.mark.parametrize("pairing", ["hash", "sort"])
-def test_small_nets_match_oracle(oracle_lib, pcx, widths, seed, incl, pairing):
+@pytest.mark.parametrize("path", ["default", "per-step"])
+def test_small_nets_match_oracle(oracle_lib, pcx, monkeypatch, widths, seed, incl, pairing, path):
+    # "default": the smallest of these networks take the batch of one (one launch of the batched kernel);
+    # "per-step": every network on the per-step kernels
+    if path == "per-step":
+        monkeypatch.setenv("PCX_NO_TINY", "1")
     net = wl.he_mlp(widths, seed)
     _compare(oracle_lib, pcx, net, wl.cube(widths[0]), incl, pairing=pairing)
+
+
+@pytest.mark.parametrize("widths,seed,incl", [([2, 8, 8, 1], 1, False), ([1, 9, 9, 1], 101, True),
+                                              ([2, 1, 1, 1], 109, False), ([3, 5, 5, 1], 110, True),
+                                              ([2, 12, 10, 1], 111, False)])
+def test_batch_of_one_equals_the_per_step_path(pcx, monkeypatch, widths, seed, incl):
+    """A small network's pcx_extract runs as a batch of one: the same arrays,
+    numbering and per-step counters as the per-step kernels give."""
+    net = wl.he_mlp(widths, seed)
+    box = wl.cube(widths[0])
+    m = pcx.MLP.from_net(net)
+    out = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("PCX_NO_TINY", off)
+        cx = pcx.extract(m, box.lo, box.hi, include_output=incl)
+        out.append((cx.copy(), cx.steps(), cx.info()))
+        cx.close()
+    m.close()
+    (a, sa, ia), (b, sb, ib) = out
+    for x, y in zip(a, b):
+        assert x.shape == y.shape and np.array_equal(x, y)
+    assert np.array_equal(sa, sb)
+    assert (ia.V, ia.E, ia.total_splits, ia.total_pairs) == (ib.V, ib.E, ib.total_splits, ib.total_pairs)
 
 
 def test_asymmetric_box(oracle_lib, pcx):
