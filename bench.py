@@ -211,24 +211,53 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v, np.float64), q)) if len(v) else 0.0
 
 
+def oracle_sample_rate(nets, boxes, threads):
+    """Oracle splits/s over a sample of networks on `threads` threads (one network
+    per thread at a time: the C oracle runs without the GIL)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build(force=False)
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(lambda nb: oracle.extract(nb[0], nb[1].lo, nb[1].hi), zip(nets, boxes)))
+    dt = time.perf_counter() - t
+    splits = sum(int(r.steps[:, 2].sum()) for r in res)
+    return splits / dt, splits, dt
+
+
 def form_batched(args, pcx, wl, torch):
     """4096 networks 2-[w]xd-1 in one persistent launch vs the per-step path."""
     nets = wl.batch_nets()
     box = wl.cube(2)
     mlps = [pcx.MLP.from_net(n) for n in nets]
     boxes = [(box.lo, box.hi)] * len(nets)
-    wpc = pcx.batch_tune(mlps, boxes)
+    tuned = pcx.batch_tune(mlps, boxes)
     for _ in range(max(1, args.warmup)):
         pcx.Batch(mlps, boxes).close()
     torch.cuda.synchronize()
+    kms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         bt = pcx.Batch(mlps, boxes)
         st = bt.stats()
+        kms.append(st.kernel_ms)
         bt.close()
     torch.cuda.synchronize()
     T = (time.perf_counter() - t0) / args.steps
-    # per-step path on a stratified sample (every 16th network), scaled by splits
+    # algorithmic bytes of every network's steps (the scope table's count), against the launch's time
+    bt = pcx.Batch(mlps, boxes)
+    b8 = sum(survey_bytes(n.widths, bt.steps(i))[0] for i, n in enumerate(nets))
+    bt.close()
+    k_med = float(np.median(kms)) / 1e3
+    achieved = b8 / k_med / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": b8, "kernel": "pcx::k_batch",
+            "launches_per_step": 1, "avg_launch_us": k_med * 1e6, "traffic": None,
+            "bytes_rule": "scope-table count summed over every network's steps; the launch also evaluates "
+                          "every layer (FP64 FMA, not in the count)"}
+    # per-step path (ordinary per-step kernels, each network once) on a stratified sample
+    os.environ["PCX_NO_TINY"] = "1"
+    os.environ["PCX_NO_GRAPH"] = "1"
     sample = list(range(0, len(nets), 16))
     t1 = time.perf_counter()
     s_splits = 0
@@ -237,18 +266,32 @@ def form_batched(args, pcx, wl, torch):
         s_splits += cx.info().total_splits
         cx.close()
     t_sample = time.perf_counter() - t1
+    del os.environ["PCX_NO_TINY"], os.environ["PCX_NO_GRAPH"]
     plain_rate = s_splits / t_sample
-    return {"metric": METRIC, "value": st.total_splits / T, "unit": "edges subdivided/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": T * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "batched: 4096 MLPs 2-[w]xd-1, w in {8,16,32,64}, d in {2,3,4}, seeds (3, i), "
-                                   "box [-1,1]^2, one persistent launch", "parallelism": "single GPU"},
-            "vertices_per_s": st.total_V / T, "edges_per_s": st.total_E / T, "V": st.total_V, "E": st.total_E,
-            "splits": st.total_splits, "kernel_ms": st.kernel_ms, "workgroups": st.workgroups,
-            "wg_per_cu_tuned": wpc, "fallbacks": st.fallbacks,
-            "plain_path": {"edges_subdivided_per_s": plain_rate, "sample": f"{len(sample)} of 4096 networks "
-                           f"extracted one by one with pcx_extract in {t_sample:.2f} s"},
-            "speedup_vs_plain": (st.total_splits / T) / plain_rate}
+    out = {"metric": METRIC, "value": st.total_splits / T, "unit": "edges subdivided/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": T * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batched: 4096 MLPs 2-[w]xd-1, w in {8,16,32,64}, d in {2,3,4}, seeds (3, i), "
+                                  "box [-1,1]^2, one persistent launch", "parallelism": "single GPU"},
+           "vertices_per_s": st.total_V / T, "edges_per_s": st.total_E / T, "V": st.total_V, "E": st.total_E,
+           "splits": st.total_splits, "kernel_ms": float(np.median(kms)), "workgroups": st.workgroups,
+           "tuned": tuned, "fallbacks": st.fallbacks, "roofline": roof,
+           "plain_path": {"edges_subdivided_per_s": plain_rate, "sample": f"{len(sample)} of 4096 networks "
+                          f"extracted one by one on the per-step kernels in {t_sample:.2f} s"},
+           "speedup_vs_plain": (st.total_splits / T) / plain_rate}
+    if not args.no_cpu_baseline:
+        osample = list(range(0, len(nets), 8))
+        snets = [nets[i] for i in osample]
+        sboxes = [box] * len(snets)
+        r1, sp1, dt1 = oracle_sample_rate(snets, sboxes, 1)
+        hc = host_cpu()
+        nth = min(16, hc["nproc"])
+        rn, spn, dtn = oracle_sample_rate(snets, sboxes, nth)
+        out["cpu_baseline"] = {"value": rn, "unit": "edges subdivided/s", "cores": nth, "kind": "oracle",
+                               "sample": f"{len(osample)} of 4096 networks (every 8th), one network per thread: "
+                                         f"{spn} splits in {dtn:.2f} s", "single_core": {"value": r1, "cores": 1,
+                                         "seconds": dt1}, **hc}
+    return out
 
 
 def form_configs(args, pcx, wl, torch):

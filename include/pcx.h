@@ -199,19 +199,34 @@ typedef struct {
     int32_t workgroups, wg_per_cu;
     double kernel_ms;       /* device time of the persistent launch */
     double time_ms;         /* host wall time of the whole call */
+    int32_t split_lanes;    /* schedule of the launch: lanes per splitting edge (32 or 64) */
+    int32_t select_items;   /*   and edges per thread in each step's compaction (16 or 8) */
 } pcx_batch_stats;
 int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
                       const pcx_opts *opts, pcx_batch **out);
 /* Per-network info / copy; PCX_ERR_DEGENERATE for a non-generic network. */
 int pcx_batch_info(const pcx_batch *bt, int32_t i, pcx_info *info);
 int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *signs, int32_t *edges);
+/* Per-step counters of network i (as pcx_complex_steps: n_steps rows of 4 int64, host). */
+int pcx_batch_steps(const pcx_batch *bt, int32_t i, int64_t *steps);
 int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *stats);
 void pcx_batch_free(pcx_batch *bt);
-/* Autotuner: runs the batch once per candidate occupancy (1, 2, 4 workgroups
- * per compute unit), keeps the fastest for batches with the same size
- * signature (used by later pcx_extract_batch calls with batch_wg_per_cu = 0). */
+/* Autotuner: times the batch's persistent launch under each schedule (lanes
+ * per splitting edge 32 or 64, edges per thread in each step's compaction 16
+ * or 8) at 2 workgroups per compute unit, then 1 and 4 workgroups per compute
+ * unit under the best schedule (best of two launches each), and keeps the
+ * fastest for batches with the same size signature (the sorted subdivided-
+ * neuron counts and input dimensions of the batched networks); later
+ * pcx_extract_batch calls of that signature use it (batch_wg_per_cu > 0 still
+ * overrides the occupancy). result (may be NULL) receives the choice. */
+typedef struct {
+    int32_t wg_per_cu, split_lanes, select_items;
+    int32_t candidates;     /* launches configurations timed */
+    double ms_default;      /* kernel time with the default schedule: 2 per CU, 32 lanes, 16 edges */
+    double ms_best;         /* kernel time with the chosen one */
+} pcx_batch_tuning;
 int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
-                   const pcx_opts *opts, int32_t *best_wg_per_cu);
+                   const pcx_opts *opts, pcx_batch_tuning *result);
 
 /* ---- Extraction server: continuous batching of requests -------------------
  * Requests are queued in arrival order and admitted in that order while the

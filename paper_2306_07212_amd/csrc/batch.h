@@ -25,6 +25,10 @@ struct BatchNet {
     StepRec *rec;  // per-step log of this network (null: not kept)
 };
 
+// schedule bits of a batched launch (0: 16 edges per thread in each step's
+// compaction, 32 lanes per splitting edge)
+enum { kSchedSelect8 = 1, kSchedSplit64 = 2, kSchedCount = 4 };
+
 struct BatchResult {
     int status, V, E, Wd;
     long long offV, offSG, offE;  // offsets into the output pool: doubles, sign words, edges
@@ -58,6 +62,6 @@ inline size_t batch_arena_bytes(size_t vbytes, int ecap, int kcap, uint32_t tcap
     return vbytes + (size_t)ecap * 16 + k + (size_t)tcap * sizeof(unsigned long long) + kBatchMaxWords * 8 + 256;
 }
 
-void launch_batch(const BatchArgs &A, int grid, hipStream_t st);
+void launch_batch(const BatchArgs &A, int grid, int sched, hipStream_t st);
 
 }  // namespace pcx

@@ -18,13 +18,34 @@
 
 namespace pcx {
 
-// Ordered compaction of {e < E : NXT[e] == target} by the whole workgroup.
+// Ordered compaction of {e < E : NXT[e] == target} by the whole workgroup,
+// SI edges per thread per round (SI = 16 or 8: a schedule choice).
+template <int SI>
+__device__ __forceinline__ uint32_t match_si(const uint16_t *__restrict__ nxt, int base, int E, uint16_t target) {
+    if (SI == 16) return match16(nxt, base, E, target);
+    uint32_t hit = 0;
+    if (base + SI <= E) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(nxt + base);
+        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if ((uint16_t)(w[i] & 0xFFFFu) == target) hit |= 1u << (2 * i);
+            if ((uint16_t)(w[i] >> 16) == target) hit |= 1u << (2 * i + 1);
+        }
+    } else {
+        for (int i = 0; i < SI; ++i)
+            if (base + i < E && nxt[base + i] == target) hit |= 1u << i;
+    }
+    return hit;
+}
+
+template <int SI>
 __device__ int block_select(const Bufs &b, int E, uint16_t target, int *s_w) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int run = 0;
-    for (int tb = 0; tb < E; tb += kSelTile) {
-        const int base = tb + t * kSelItems;
-        uint32_t hit = base < E ? match16(b.NXT, base, E, target) : 0u;
+    for (int tb = 0; tb < E; tb += kThreads * SI) {
+        const int base = tb + t * SI;
+        uint32_t hit = base < E ? match_si<SI>(b.NXT, base, E, target) : 0u;
         const int cnt = __popc(hit);
         int incl = cnt;
 #pragma unroll
@@ -98,6 +119,10 @@ __device__ __forceinline__ void block_split(const Bufs &b, const StepGeom &g, in
     for (int s = grp; s < S; s += groups) split_one<G, NC>(b, g, V0, E0, s, lane, half, S * g.P);
 }
 
+// One network, whole, by the workgroup. Schedule (chosen per size bucket by
+// the autotuner): SI edges per thread in each step's compaction, GS lanes per
+// splitting edge.
+template <int SI, int GS>
 __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b, GemmLds *gl, int *s_w,
                         int *s_misc) {
     const int t = threadIdx.x;
@@ -198,7 +223,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             break;
         }
         for (int j = 0; j < N; ++j, ++step) {
-            const int S = block_select(b, E, (uint16_t)j, s_w);
+            const int S = block_select<SI>(b, E, (uint16_t)j, s_w);
             if (S == 0) {
                 if (t == 0 && net.rec) net.rec[step] = StepRec{V, E, 0, E};
                 continue;
@@ -233,10 +258,16 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                 for (uint32_t i = t; i < tsz; i += kThreads) table[i] = 0ull;
                 __syncthreads();
             }
-            if (N <= 32) block_split<32, 1>(b, g, V, E, S);
-            else if (N <= 64) block_split<32, 2>(b, g, V, E, S);
-            else if (N <= 128) block_split<32, 4>(b, g, V, E, S);
-            else block_split<32, 8>(b, g, V, E, S);
+            if (GS == 32) {
+                if (N <= 32) block_split<32, 1>(b, g, V, E, S);
+                else if (N <= 64) block_split<32, 2>(b, g, V, E, S);
+                else if (N <= 128) block_split<32, 4>(b, g, V, E, S);
+                else block_split<32, 8>(b, g, V, E, S);
+            } else {
+                if (N <= 64) block_split<64, 1>(b, g, V, E, S);
+                else if (N <= 128) block_split<64, 2>(b, g, V, E, S);
+                else block_split<64, 4>(b, g, V, E, S);
+            }
             __syncthreads();
             // the pairing reads partner records other waves of this workgroup stored: past the L1
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -303,6 +334,8 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
     __syncthreads();
 }
 
+// the persistent kernel for one schedule (SI, GS) of the whole batch
+template <int SI, int GS>
 __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
     __shared__ GemmLds gl;
     __shared__ int s_w[kThreads / 64];
@@ -316,12 +349,19 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
         __syncthreads();
         if (k >= A.n) break;
         const int ni = A.order[k];
-        run_net(A, A.nets[ni], ni, b, &gl, s_w, s_misc);
+        run_net<SI, GS>(A, A.nets[ni], ni, b, &gl, s_w, s_misc);
     }
 }
 
-void launch_batch(const BatchArgs &A, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), 0, st, A);
+void launch_batch(const BatchArgs &A, int grid, int sched, hipStream_t st) {
+    switch (sched) {
+        case kSchedSelect8: hipLaunchKernelGGL((k_batch<8, 32>), dim3(grid), dim3(kThreads), 0, st, A); break;
+        case kSchedSplit64: hipLaunchKernelGGL((k_batch<16, 64>), dim3(grid), dim3(kThreads), 0, st, A); break;
+        case kSchedSelect8 | kSchedSplit64:
+            hipLaunchKernelGGL((k_batch<8, 64>), dim3(grid), dim3(kThreads), 0, st, A);
+            break;
+        default: hipLaunchKernelGGL((k_batch<16, 32>), dim3(grid), dim3(kThreads), 0, st, A); break;
+    }
 }
 
 }  // namespace pcx

@@ -21,6 +21,8 @@ struct pcx_batch {
     int2 *oE = nullptr;
     double time_ms = 0.0, kernel_ms = 0.0;
     int workgroups = 0, wg_per_cu = 0, n_fallback = 0;
+    int sched = 0;                            // schedule bits of the launch (kSched*)
+    std::vector<int> sig;                     // size signature of the batched networks
     std::vector<std::vector<int64_t>> steps;  // per-step counters of each batched network (when kept)
     std::vector<int> nsub, ZS;
     std::vector<std::vector<uint64_t>> valid;
@@ -28,8 +30,17 @@ struct pcx_batch {
 
 namespace {
 
+// the autotuner's choices: batch size signature -> (workgroups per CU, schedule bits)
 std::mutex g_tune_mu;
-std::map<std::vector<int>, int> g_tuned;  // batch signature -> workgroups per CU
+std::map<std::vector<int>, std::pair<int, int>> g_tuned;
+
+// size signature of a batch: the sorted (subdivided neurons, D) of its batched networks
+std::vector<int> signature(const std::vector<int> &nsteps, const std::vector<int> &D, const std::vector<int> &idx) {
+    std::vector<int> sig;
+    for (int i : idx) sig.push_back(nsteps[i] * 16 + D[i]);
+    std::sort(sig.begin(), sig.end());
+    return sig;
+}
 
 }  // namespace
 
@@ -38,7 +49,7 @@ namespace {
 // The batched extraction; with keep_steps, every batched network's per-step
 // counters are logged too (the batch of one behind small pcx_extract calls).
 int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi, const pcx_opts *opts,
-              bool keep_steps, pcx_batch **out) {
+              bool keep_steps, pcx_batch **out, int force_sched = -1) {
     if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (n < 0 || (n > 0 && (!mlps || !lo || !hi))) return fail(PCX_ERR_INVALID, "NULL argument");
@@ -156,17 +167,26 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
         while (tcap < 2u * (uint32_t)kcap) tcap <<= 1;
         size_t abytes = batch_arena_bytes(vbytes, ecap, kcap, tcap);
         abytes = (abytes + 255) / 256 * 256;
-        // workgroups per CU: from the autotuner's cache, else 2
-        std::vector<int> sig;
-        for (int i : batched) sig.push_back(bt->nsteps[i] * 16 + bt->D[i]);
-        std::sort(sig.begin(), sig.end());
-        int wpc = 2;
+        // workgroups per CU and schedule: from the autotuner's cache, else 2 and the default
+        const std::vector<int> sig = signature(bt->nsteps, bt->D, batched);
+        bt->sig = sig;
+        int wpc = 2, sched = 0;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find(sig);
-            if (it != g_tuned.end()) wpc = it->second;
+            if (it != g_tuned.end()) {
+                wpc = it->second.first;
+                sched = it->second.second;
+            }
         }
         if (o.batch_wg_per_cu > 0) wpc = o.batch_wg_per_cu;
+        if (force_sched < 0) {
+            // test hook: one schedule for every launch (0 .. kSchedCount-1)
+            const char *v = getenv("PCX_BATCH_SCHED");
+            if (v && *v) force_sched = std::max(0, std::min(kSchedCount - 1, atoi(v)));
+        }
+        if (force_sched >= 0) sched = force_sched;
+        bt->sched = sched;
         int grid = std::min<int>((int)batched.size(), cus * wpc);
         // output pool from the predictions (overflowing networks fall back)
         double sv = 0, ssg = 0, se = 0;
@@ -239,7 +259,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
             HIPCHK(hipEventCreate(&e0));
             HIPCHK(hipEventCreate(&e1));
             HIPCHK(hipEventRecord(e0, st));
-            launch_batch(A, grid, st);
+            launch_batch(A, grid, sched, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipEventRecord(e1, st));
             HIPCHK(hipMemcpyAsync(bt->res.data(), A.res, (size_t)n * sizeof(BatchResult), hipMemcpyDeviceToHost, st));
@@ -318,7 +338,7 @@ fail_out:
 
 extern "C" int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
                                  const pcx_opts *opts, pcx_batch **out) {
-    return batch_run(n, mlps, lo, hi, opts, false, out);
+    return batch_run(n, mlps, lo, hi, opts, true, out);
 }
 
 namespace pcx {
@@ -404,6 +424,15 @@ int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *sig
     return PCX_OK;
 }
 
+int pcx_batch_steps(const pcx_batch *bt, int32_t i, int64_t *steps) {
+    if (!bt || !steps || i < 0 || i >= bt->n) return fail(PCX_ERR_INVALID, "bad argument");
+    const BatchResult &r = bt->res[i];
+    if (r.status == BATCH_DEGENERATE) return fail(PCX_ERR_DEGENERATE, "network is not generic");
+    if (bt->fallback[i]) return pcx_complex_steps(bt->fallback[i], steps);
+    std::memcpy(steps, bt->steps[i].data(), bt->steps[i].size() * sizeof(int64_t));
+    return PCX_OK;
+}
+
 int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *s) {
     if (!bt || !s) return fail(PCX_ERR_INVALID, "NULL argument");
     std::memset(s, 0, sizeof *s);
@@ -421,6 +450,8 @@ int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *s) {
     s->fallbacks = bt->n_fallback;
     s->workgroups = bt->workgroups;
     s->wg_per_cu = bt->wg_per_cu;
+    s->split_lanes = (bt->sched & kSchedSplit64) ? 64 : 32;
+    s->select_items = (bt->sched & kSchedSelect8) ? 8 : 16;
     s->kernel_ms = bt->kernel_ms;
     s->time_ms = bt->time_ms;
     return PCX_OK;
@@ -436,39 +467,56 @@ void pcx_batch_free(pcx_batch *bt) {
 }
 
 int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi, const pcx_opts *opts,
-                   int32_t *best_wg_per_cu) {
-    // try each occupancy, keep the fastest for this batch's size signature
-    static const int cand[] = {1, 2, 4};
-    double best = 1e300;
-    int bw = 2;
-    for (int w : cand) {
-        pcx_opts o{};
-        if (opts) o = *opts;
-        o.batch_wg_per_cu = w;
-        pcx_batch *bt = nullptr;
-        int rc = pcx_extract_batch(n, mlps, lo, hi, &o, &bt);
-        if (rc) return rc;
-        if (bt->kernel_ms < best) {
-            best = bt->kernel_ms;
-            bw = w;
-        }
-        pcx_batch_free(bt);
-    }
+                   pcx_batch_tuning *result) {
+    // time the batch's launch under each schedule at two workgroups per CU,
+    // then each occupancy under the best schedule (best of two launches each)
     std::vector<int> sig;
-    const int incl = opts ? opts->include_output : 0;
-    for (int i = 0; i < n; ++i) {
-        int N = 0;
-        const int nsub = incl ? mlps[i]->L : mlps[i]->L - 1;
-        for (int l = 1; l <= nsub; ++l) N += mlps[i]->widths[l];
-        if (predict_vertices(mlps[i]->D, N) <= 65536.0 && mlps[i]->D <= kBatchMaxD && mlps[i]->L <= kBatchMaxLayers)
-            sig.push_back(N * 16 + mlps[i]->D);
+    auto measure = [&](int wpc, int sched, double *ms) -> int {
+        *ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            pcx_opts o{};
+            if (opts) o = *opts;
+            o.batch_wg_per_cu = wpc;
+            pcx_batch *bt = nullptr;
+            int rc = batch_run(n, mlps, lo, hi, &o, false, &bt, sched);
+            if (rc) return rc;
+            *ms = std::min(*ms, bt->kernel_ms);
+            sig = bt->sig;
+            pcx_batch_free(bt);
+        }
+        return PCX_OK;
+    };
+    int rc, best_sched = 0, best_wpc = 2, tried = 0;
+    double ms_default = 0, best = 1e300, ms;
+    for (int sc = 0; sc < kSchedCount; ++sc) {
+        if ((rc = measure(2, sc, &ms))) return rc;
+        ++tried;
+        if (sc == 0) ms_default = ms;
+        if (ms < best) {
+            best = ms;
+            best_sched = sc;
+        }
     }
-    std::sort(sig.begin(), sig.end());
+    for (int w : {1, 4}) {
+        if ((rc = measure(w, best_sched, &ms))) return rc;
+        ++tried;
+        if (ms < best) {
+            best = ms;
+            best_wpc = w;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[sig] = bw;
+        g_tuned[sig] = {best_wpc, best_sched};
     }
-    if (best_wg_per_cu) *best_wg_per_cu = bw;
+    if (result) {
+        result->wg_per_cu = best_wpc;
+        result->split_lanes = (best_sched & kSchedSplit64) ? 64 : 32;
+        result->select_items = (best_sched & kSchedSelect8) ? 8 : 16;
+        result->candidates = tried;
+        result->ms_default = ms_default;
+        result->ms_best = best;
+    }
     return PCX_OK;
 }
 

@@ -337,7 +337,9 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     // the per-column predicates below (c < N, c vs j, c >= zlo) are cheap to
     // recompute; an empty asm makes their bounds opaque per split so that they
     // are not hoisted out of the caller's loop into dozens of live lane masks
-    int j = g.j, N = g.Nl, zlo = g.zlo;
+    // (uniform values: readfirstlane keeps them in scalar registers in every caller)
+    int j = __builtin_amdgcn_readfirstlane(g.j), N = __builtin_amdgcn_readfirstlane(g.Nl),
+        zlo = __builtin_amdgcn_readfirstlane(g.zlo);
     asm volatile("" : "+s"(j), "+s"(N), "+s"(zlo));
     const int nw = g.lw1 - g.lw0;
     const double *Za = b.Z + (size_t)ab.x * ZS, *Zb = b.Z + (size_t)ab.y * ZS;

@@ -41,6 +41,7 @@ SYMBOLS = [
     "pcx_extract_batch", "pcx_batch_info", "pcx_batch_copy", "pcx_batch_summary", "pcx_batch_free",
     "pcx_batch_tune", "pcx_server_create", "pcx_server_submit", "pcx_server_poll", "pcx_server_wait",
     "pcx_server_copy", "pcx_server_release", "pcx_server_stats", "pcx_server_destroy", "pcx_extract_into",
+    "pcx_batch_steps",
 ]
 PCX_F64, PCX_F32 = 0, 1
 
@@ -60,7 +61,13 @@ class _Opts(C.Structure):
 class _BatchStats(C.Structure):
     _fields_ = [("n", C.c_int64), ("total_V", C.c_int64), ("total_E", C.c_int64), ("total_splits", C.c_int64),
                 ("fallbacks", C.c_int32), ("degenerate", C.c_int32), ("workgroups", C.c_int32),
-                ("wg_per_cu", C.c_int32), ("kernel_ms", C.c_double), ("time_ms", C.c_double)]
+                ("wg_per_cu", C.c_int32), ("kernel_ms", C.c_double), ("time_ms", C.c_double),
+                ("split_lanes", C.c_int32), ("select_items", C.c_int32)]
+
+
+class _BatchTuning(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_int32), ("split_lanes", C.c_int32), ("select_items", C.c_int32),
+                ("candidates", C.c_int32), ("ms_default", C.c_double), ("ms_best", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -115,10 +122,11 @@ def _load():
     lib.pcx_extract_batch.argtypes = [i32, C.POINTER(vp), PD, PD, C.POINTER(_Opts), C.POINTER(vp)]
     lib.pcx_batch_info.argtypes = [vp, i32, C.POINTER(_Info)]
     lib.pcx_batch_copy.argtypes = [vp, i32, vp, vp, vp]
+    lib.pcx_batch_steps.argtypes = [vp, i32, vp]
     lib.pcx_batch_summary.argtypes = [vp, C.POINTER(_BatchStats)]
     lib.pcx_batch_free.argtypes = [vp]
     lib.pcx_batch_free.restype = None
-    lib.pcx_batch_tune.argtypes = [i32, C.POINTER(vp), PD, PD, C.POINTER(_Opts), C.POINTER(i32)]
+    lib.pcx_batch_tune.argtypes = [i32, C.POINTER(vp), PD, PD, C.POINTER(_Opts), C.POINTER(_BatchTuning)]
     u64p = C.POINTER(C.c_uint64)
     lib.pcx_server_create.argtypes = [C.POINTER(_ServerOpts), C.POINTER(vp)]
     lib.pcx_server_submit.argtypes = [vp, vp, PD, PD, u64p]
@@ -397,6 +405,8 @@ class BatchStats:
     wg_per_cu: int
     kernel_ms: float
     time_ms: float
+    split_lanes: int = 32
+    select_items: int = 16
 
 
 def _batch_args(mlps, boxes):
@@ -437,11 +447,17 @@ class Batch:
         _check(_lib.pcx_batch_copy(self._h, int(i), X.ctypes.data, SG.ctypes.data, Ed.ctypes.data))
         return X, SG, Ed
 
+    def steps(self, i) -> np.ndarray:
+        """Per-step counters of network i ([n_steps, 4] int64, as Complex.steps)."""
+        out = np.zeros((self.info(i).n_steps, 4), np.int64)
+        _check(_lib.pcx_batch_steps(self._h, int(i), out.ctypes.data))
+        return out
+
     def stats(self) -> BatchStats:
         x = _BatchStats()
         _check(_lib.pcx_batch_summary(self._h, C.byref(x)))
         return BatchStats(x.n, x.total_V, x.total_E, x.total_splits, x.fallbacks, x.degenerate, x.workgroups,
-                          x.wg_per_cu, x.kernel_ms, x.time_ms)
+                          x.wg_per_cu, x.kernel_ms, x.time_ms, x.split_lanes, x.select_items)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -454,15 +470,16 @@ class Batch:
             self.close()
 
 
-def batch_tune(mlps, boxes, include_output: bool = False) -> int:
-    """``pcx_batch_tune``: best workgroups per compute unit for this batch's sizes."""
+def batch_tune(mlps, boxes, include_output: bool = False) -> dict:
+    """``pcx_batch_tune``: the schedule and occupancy chosen for this batch's
+    size signature (and the kernel times with the default and chosen ones)."""
     arr, lo, hi = _batch_args(list(mlps), boxes)
     PD = C.POINTER(C.c_double)
     o = _Opts(int(bool(include_output)), 0, 0, 0, 0, None, 0, 0)
-    best = C.c_int32()
+    r = _BatchTuning()
     _check(_lib.pcx_batch_tune(len(mlps), arr, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o),
-                               C.byref(best)))
-    return best.value
+                               C.byref(r)))
+    return _as_dict(r)
 
 
 def _as_dict(st):

@@ -25,7 +25,8 @@ def plain(pcx, net, box, incl=False):
     return out
 
 
-def test_batch_bit_identical_to_plain(pcx, oracle_lib):
+def test_batch_bit_identical_to_plain(pcx, oracle_lib, monkeypatch):
+    monkeypatch.setenv("PCX_NO_TINY", "1")  # the reference is the per-step kernels
     nets = wl.batch_nets(96)
     boxes = [(wl.cube(2).lo, wl.cube(2).hi)] * len(nets)
     mlps = [pcx.MLP.from_net(n) for n in nets]
@@ -44,7 +45,8 @@ def test_batch_bit_identical_to_plain(pcx, oracle_lib):
     bt.close()
 
 
-def test_batch_mixed_dims_output_fallback_and_degenerate(pcx, oracle_lib):
+def test_batch_mixed_dims_output_fallback_and_degenerate(pcx, oracle_lib, monkeypatch):
+    monkeypatch.setenv("PCX_NO_TINY", "1")  # the reference is the per-step kernels
     nets = [wl.he_mlp([2, 12, 12, 1], 201), wl.he_mlp([3, 10, 10, 1], 202), wl.he_mlp([1, 9, 9, 9, 1], 203),
             wl.he_mlp([3, 64, 64, 64, 1], 5),          # too large for the batched kernel: per-step path
             wl.Net([2, 1, 1], [np.array([[1.0, 1.0]]), np.array([[1.0]])], [np.zeros(1), np.zeros(1)]),  # not generic
@@ -70,12 +72,13 @@ def test_batch_mixed_dims_output_fallback_and_degenerate(pcx, oracle_lib):
     bt.close()
 
 
-def test_batch_full_workload_every_network(pcx, oracle_lib):
+def test_batch_full_workload_every_network(pcx, oracle_lib, monkeypatch):
     """All 4096 networks of the batched workload in one launch: every network
     bit-identical to its per-step extraction (values and numbering) and equal
     to the oracle's complex in canonical form (signs and incidence exact,
     coordinates within 1e-10)."""
     from conftest import oracle_pool
+    monkeypatch.setenv("PCX_NO_TINY", "1")  # the reference is the per-step kernels
     nets = wl.batch_nets()
     box = wl.cube(2)
     pool = oracle_pool()
@@ -90,6 +93,7 @@ def test_batch_full_workload_every_network(pcx, oracle_lib):
         got = bt.copy(i)
         cx = pcx.extract(mlps[i], box.lo, box.hi)
         ref = cx.copy()
+        steps = cx.steps()
         cx.close()
         for a, b in zip(got, ref):
             assert a.shape == b.shape and np.array_equal(a, b), f"network {i} differs from the per-step path"
@@ -99,6 +103,8 @@ def test_batch_full_workload_every_network(pcx, oracle_lib):
         assert_same_complex((X, unpack_signs(SG, net.widths), Ed), (r.X, r.S, r.edges))
         info = bt.info(i)
         assert (info.V, info.E, info.total_splits) == (r.V, r.E, int(r.steps[:, 2].sum()))
+        assert np.array_equal(bt.steps(i), r.steps), f"network {i}: per-step counters"
+        assert np.array_equal(bt.steps(i), steps), f"network {i}: per-step counters vs the per-step path"
         tot[0] += r.V
         tot[1] += r.E
         tot[2] += int(r.steps[:, 2].sum())
@@ -109,3 +115,40 @@ def test_batch_full_workload_every_network(pcx, oracle_lib):
     bt.close()
     for m in mlps:
         m.close()
+
+
+def test_batch_schedules_and_tuner(pcx, monkeypatch):
+    """Every launch schedule (lanes per splitting edge, edges per thread in the
+    compaction) gives the same complexes, and the autotuner's choice is one of
+    them, no slower than the default it was timed against."""
+    monkeypatch.setenv("PCX_NO_TINY", "1")
+    nets = wl.batch_nets(256)
+    box = wl.cube(2)
+    mlps = [pcx.MLP.from_net(n) for n in nets]
+    boxes = [(box.lo, box.hi)] * len(nets)
+    ref = None
+    for sc in range(4):
+        monkeypatch.setenv("PCX_BATCH_SCHED", str(sc))
+        bt = pcx.Batch(mlps, boxes)
+        st = bt.stats()
+        assert (st.split_lanes, st.select_items) == (64 if sc & 2 else 32, 8 if sc & 1 else 16)
+        got = [bt.copy(i) for i in range(len(nets))]
+        bt.close()
+        if ref is None:
+            ref = got
+            continue
+        for i, (a, b) in enumerate(zip(got, ref)):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), f"schedule {sc}, network {i}"
+    monkeypatch.delenv("PCX_BATCH_SCHED")
+    t = pcx.batch_tune(mlps, boxes)
+    print(f"tuned: {t}", flush=True)
+    assert t["wg_per_cu"] in (1, 2, 4) and t["split_lanes"] in (32, 64) and t["select_items"] in (8, 16)
+    assert t["candidates"] == 6 and t["ms_best"] <= t["ms_default"]
+    bt = pcx.Batch(mlps, boxes)
+    st = bt.stats()
+    assert (st.wg_per_cu, st.split_lanes, st.select_items) == (t["wg_per_cu"], t["split_lanes"], t["select_items"])
+    for i in range(0, len(nets), 17):
+        for x, y in zip(bt.copy(i), ref[i]):
+            assert np.array_equal(x, y)
+    bt.close()
