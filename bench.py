@@ -375,13 +375,20 @@ def form_served(args, pcx, wl, torch):
     reqs = wl.serve_requests(2000, rate_per_s=1.0)
     unit = np.array([r.arrival_s for r in reqs])          # unit-rate arrival times
     mlps = [pcx.MLP.from_net(r.net) for r in reqs]
+    # the per-step path as the server's own workers run it (no graph replay of repeated requests)
+    os.environ["PCX_NO_GRAPH"] = "1"
+    for r, m in zip(reqs[:100], mlps[:100]):  # warm the device memory pool
+        pcx.extract(m, r.box.lo, r.box.hi).close()
     # per-step path: service time of every request alone
     svc = np.empty(len(reqs))
+    alone = np.empty((len(reqs), 3), np.int64)  # V, E, splits of each request extracted alone
     for i, (r, m) in enumerate(zip(reqs, mlps)):
         t = time.perf_counter()
         cx = pcx.extract(m, r.box.lo, r.box.hi)
+        info = cx.info()
         cx.close()
         svc[i] = time.perf_counter() - t
+        alone[i] = (info.V, info.E, info.total_splits)
         if i % 250 == 0:
             print(f"[bench] served: plain service times {i}/{len(reqs)}", file=sys.stderr, flush=True)
     mu = len(reqs) / svc.sum()  # saturation throughput of the per-step path (requests/s)
@@ -428,21 +435,77 @@ def form_served(args, pcx, wl, torch):
         if failed:
             print(f"[bench] served: {len(failed)} requests failed, first: {failed[:3]}", file=sys.stderr, flush=True)
             raise SystemExit(f"served requests failed: {failed[:3]}")
+        got = np.array([(x["V"], x["E"], x["total_splits"]) for x in res], np.int64)
+        bad = np.nonzero(np.any(got != alone, axis=1))[0]
+        if len(bad):
+            raise SystemExit(f"served results differ from the same requests extracted alone: {bad[:5].tolist()}")
+        live = None
+        if f in (1.0, 2.0):
+            # the per-step path as a live FIFO single server under the same arrivals
+            lat = np.empty(len(reqs))
+            t0 = time.perf_counter()
+            for i, (a, r, m) in enumerate(zip(arr, reqs, mlps)):
+                dt = a - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                cx = pcx.extract(m, r.box.lo, r.box.hi)
+                cx.close()
+                lat[i] = (time.perf_counter() - t0 - a) * 1e3
+                if i % 500 == 0:
+                    print(f"[bench] served: live FIFO {i}/{len(reqs)}", file=sys.stderr, flush=True)
+            live = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "jobs_per_s": len(reqs) / (time.perf_counter() - t0)}
         out_rates.append({"rate_x_plain_saturation": f, "rate_per_s": lam,
                           "served": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "jobs_per_s": st["jobs_per_s"],
                                      "splits_per_s": st["splits_per_s"], "ticks": st["ticks"],
                                      "mean_tick_jobs": st["mean_tick_jobs"],
                                      "batched_fraction": float(np.mean([x["batched"] for x in res]))},
                           "plain_fifo": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
-                                         "jobs_per_s": len(reqs) / fin[-1]}})
+                                         "jobs_per_s": len(reqs) / fin[-1],
+                                         "from": "queue of the measured alone service times"},
+                          "plain_fifo_live": live, "results_checked": len(reqs)})
         print(f"[bench] served rate {f}x: {json.dumps(out_rates[-1])}", file=sys.stderr, flush=True)
     mid = out_rates[2]
-    return {"metric": METRIC, "value": mid["served"]["p99_ms"], "unit": "ms (p99 latency at the plain path's "
-            "saturation rate)", "n_gpus": 1, "steps": len(reqs), "warmup": 0, "higher_is_better": False,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "served: Poisson stream of 2000 requests, D in {2,3}, constant width U[16,128], "
-                                   "depth U{2,3,4}, box [-1,1]^D, seeds (4, i)", "parallelism": "single GPU"},
-            "plain_saturation_req_per_s": mu, "plain_mean_service_ms": float(svc.mean() * 1e3), "rates": out_rates}
+    out = {"metric": METRIC, "value": mid["served"]["p99_ms"], "unit": "ms (p99 latency at the plain path's "
+           "saturation rate)", "n_gpus": 1, "steps": len(reqs), "warmup": 0, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "served: Poisson stream of 2000 requests, D in {2,3}, constant width U[16,128], "
+                                  "depth U{2,3,4}, box [-1,1]^D, seeds (4, i)", "parallelism": "single GPU"},
+           "plain_saturation_req_per_s": mu, "plain_mean_service_ms": float(svc.mean() * 1e3),
+           "plain_service_ms": {"p50": pct(svc * 1e3, 50), "p99": pct(svc * 1e3, 99)}, "rates": out_rates}
+    del os.environ["PCX_NO_GRAPH"]
+    if not args.no_cpu_baseline:
+        # the oracle's service times (one core) on every 10th request among those with at most
+        # 20K splits (the largest requests would take the oracle minutes each), beside the GPU
+        # per-step path's alone service times on the same requests; then the oracle's throughput
+        # on that subset with one request per thread on all host cores
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        oracle.build(force=False)
+        sample = [i for i in range(0, len(reqs), 10) if alone[i, 2] <= 20000]
+        ts = []
+        for k, i in enumerate(sample):
+            t = time.perf_counter()
+            oracle.extract(reqs[i].net, reqs[i].box.lo, reqs[i].box.hi)
+            ts.append(time.perf_counter() - t)
+            if k % 40 == 0:
+                print(f"[bench] served: oracle {k}/{len(sample)}", file=sys.stderr, flush=True)
+        ts = np.array(ts) * 1e3
+        hc = host_cpu()
+        nth = min(16, hc["nproc"])
+        t = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=nth) as ex:
+            list(ex.map(lambda i: oracle.extract(reqs[i].net, reqs[i].box.lo, reqs[i].box.hi), sample))
+        dt = time.perf_counter() - t
+        g = svc[sample] * 1e3
+        out["cpu_baseline"] = {"value": float(np.percentile(ts, 99)), "unit": "ms (p99 service time, one core, "
+                               "no queueing)", "cores": 1, "kind": "oracle",
+                               "sample": f"{len(sample)} requests: every 10th of the 2000 with at most 20000 "
+                                         f"splits (of {len(range(0, len(reqs), 10))})",
+                               "p50_ms": float(np.percentile(ts, 50)), "mean_ms": float(ts.mean()),
+                               "gpu_plain_same_requests": {"p50_ms": pct(g, 50), "p99_ms": pct(g, 99),
+                                                           "mean_ms": float(g.mean())},
+                               "all_cores": {"cores": nth, "requests_per_s": len(sample) / dt}, **hc}
+    return out
 
 
 def form_backward(args, pcx, wl, torch):

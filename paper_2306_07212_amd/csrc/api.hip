@@ -37,6 +37,26 @@ Pool &pool() {
     return *p;
 }
 
+std::shared_mutex &capture_gate() {
+    static std::shared_mutex g;
+    return g;
+}
+
+int copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+    if (!bytes) return PCX_OK;
+    thread_local std::unordered_map<int, hipStream_t> *streams = new std::unordered_map<int, hipStream_t>();
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipStream_t &s = (*streams)[dev];
+    if (!s) {
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
+        HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    }
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, kind, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PCX_OK;
+}
+
 }  // namespace pcx
 
 using namespace pcx;
@@ -81,6 +101,7 @@ int host_res(HostRes *&out) {
     HIPCHK(hipGetDevice(&dev));
     HostRes *&r = (*per_dev)[dev];
     if (!r) {
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
         auto *n = new HostRes();
         HIPCHK(hipHostMalloc((void **)&n->pinned, 3 * CTR_COUNT * sizeof(int), hipHostMallocDefault));
         for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&n->snap[i], hipEventDisableTiming));
@@ -419,6 +440,7 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
         for (int i = 0; i < nout; ++i)
             for (int k = 0; k < nin; ++k) tmp[(size_t)k * nout + i] = W[l][(size_t)i * nin + k];
         double *dw = nullptr, *db = nullptr;
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
         if (hipMalloc((void **)&dw, tmp.size() * sizeof(double)) != hipSuccess ||
             hipMalloc((void **)&db, (size_t)nout * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
@@ -435,9 +457,10 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
             return fail(PCX_ERR_OOM, "hipMalloc for weights failed");
         }
         m->Wr.push_back(dr);
-        if (hipMemcpy(dw, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(dr, W[l], tmp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(db, b[l], (size_t)nout * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        gate.unlock();
+        if (copy_sync(dw, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice) ||
+            copy_sync(dr, W[l], tmp.size() * sizeof(double), hipMemcpyHostToDevice) ||
+            copy_sync(db, b[l], (size_t)nout * sizeof(double), hipMemcpyHostToDevice)) {
             pcx_mlp_free(m);
             return fail(PCX_ERR_DEVICE, "copying weights to the device failed");
         }
@@ -449,6 +472,7 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
 void pcx_mlp_free(pcx_mlp *m) {
     if (!m) return;
     graph_cache_free(m->gcache);
+    std::shared_lock<std::shared_mutex> gate(capture_gate());
     for (auto p : m->Wt) (void)hipFree(p);
     for (auto p : m->Wr) (void)hipFree(p);
     for (auto p : m->b) (void)hipFree(p);
@@ -489,12 +513,13 @@ bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
 }
 
 int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pcx_complex **out,
-                 bool tiny_ok = false) {
+                 int shortcuts = 0) {
     pcx_opts o{};
     if (opts) o = *opts;
     const int D = mlp->D, L = mlp->L;
     const int nsub = o.include_output ? L : L - 1;
-    if (tiny_ok && dom.lo && tiny_eligible(mlp, o, nsub)) return tiny_extract(mlp, dom.lo, dom.hi, o, out);
+    if ((shortcuts & kShortcutTiny) && dom.lo && tiny_eligible(mlp, o, nsub))
+        return tiny_extract(mlp, dom.lo, dom.hi, o, out);
     std::vector<int> lw(nsub + 1);
     lw[0] = 1;
     int M = dom.m, ZS = 1, n_steps = 0;
@@ -537,7 +562,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     const bool box = dom.lo != nullptr;
     const size_t V0 = box ? (size_t)1 << D : dom.W0.size(), E0 = box ? (size_t)D << (D - 1) : dom.E0.size();
     if ((rc = x.attach_host())) return rc;
-    if (dom.lo) {
+    if ((shortcuts & kShortcutGraph) && dom.lo) {
         // a repeat of the network's last extraction: its captured graph
         rc = graph_try(mlp, dom.lo, dom.hi, o, st, x.res->cap, x.res->t0, x.res->t1, x.res->pinned, out);
         if (rc != kGraphDeclined) return rc;
@@ -948,7 +973,8 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     int64_t total_splits = 0, Smax = 0;
     if (lagged && n_steps > 0) {
         std::vector<StepRec> rec(n_steps);
-        HIPCHK(hipMemcpy(rec.data(), x.b.REC, n_steps * sizeof(StepRec), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(rec.data(), x.b.REC, n_steps * sizeof(StepRec), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         for (int t = 0; t < n_steps; ++t) {
             steps[(size_t)t * 4 + 0] = rec[t].V0;
             steps[(size_t)t * 4 + 1] = rec[t].E0;
@@ -1019,7 +1045,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
     m->hintV.store(std::max<int64_t>(m->hintV.load(), V));
     m->hintE.store(std::max<int64_t>(m->hintE.load(), Ebound));
     m->hintS.store(std::max<int64_t>(m->hintS.load(), Smax));
-    if (dom.lo) graph_record(mlp, dom.lo, dom.hi, o, cx, Ebound, Smax);
+    if ((shortcuts & kShortcutGraph) && dom.lo) graph_record(mlp, dom.lo, dom.hi, o, cx, Ebound, Smax);
     *out = cx;
     return PCX_OK;
 }
@@ -1027,12 +1053,13 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
 }  // namespace
 
 namespace pcx {
-int extract_ordinary(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out) {
+int extract_ordinary(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out,
+                     int shortcuts) {
     Domain dom;
     dom.m = 2 * mlp->D;
     dom.lo = lo;
     dom.hi = hi;
-    return extract_impl(mlp, dom, opts, out, false);
+    return extract_impl(mlp, dom, opts, out, shortcuts);
 }
 
 }  // namespace pcx
@@ -1049,7 +1076,7 @@ int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pc
     dom.m = 2 * mlp->D;
     dom.lo = lo;
     dom.hi = hi;
-    return extract_impl(mlp, dom, opts, out, true);
+    return extract_impl(mlp, dom, opts, out, kShortcutTiny | kShortcutGraph);
 }
 
 int pcx_extract_simplex(const pcx_mlp *mlp, const double *corners, const pcx_opts *opts, pcx_complex **out) {
@@ -1120,9 +1147,13 @@ int pcx_complex_steps(const pcx_complex *cx, int64_t *steps) {
 
 int pcx_complex_copy(const pcx_complex *cx, double *coords, uint64_t *signs, int32_t *edges) {
     if (!cx) return fail(PCX_ERR_INVALID, "NULL complex");
-    if (coords) HIPCHK(hipMemcpy(coords, cx->X, (size_t)cx->V * cx->D * sizeof(double), hipMemcpyDeviceToHost));
-    if (signs) HIPCHK(hipMemcpy(signs, cx->SG, (size_t)cx->V * cx->Wd * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    if (edges) HIPCHK(hipMemcpy(edges, cx->EDG, (size_t)cx->E * 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int rc;
+    if (coords && (rc = copy_sync(coords, cx->X, (size_t)cx->V * cx->D * sizeof(double), hipMemcpyDeviceToHost)))
+        return rc;
+    if (signs && (rc = copy_sync(signs, cx->SG, (size_t)cx->V * cx->Wd * sizeof(uint64_t), hipMemcpyDeviceToHost)))
+        return rc;
+    if (edges && (rc = copy_sync(edges, cx->EDG, (size_t)cx->E * 2 * sizeof(int32_t), hipMemcpyDeviceToHost)))
+        return rc;
     return PCX_OK;
 }
 

@@ -416,11 +416,15 @@ int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *sig
     if (r.status == BATCH_DEGENERATE) return fail(PCX_ERR_DEGENERATE, "network is not generic");
     if (bt->fallback[i]) return pcx_complex_copy(bt->fallback[i], coords, signs, edges);
     const int D = bt->D[i];
-    if (coords)
-        HIPCHK(hipMemcpy(coords, bt->oX + (size_t)r.offV, (size_t)r.V * D * sizeof(double), hipMemcpyDeviceToHost));
-    if (signs)
-        HIPCHK(hipMemcpy(signs, bt->oSG + r.offSG, (size_t)r.V * r.Wd * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    if (edges) HIPCHK(hipMemcpy(edges, bt->oE + r.offE, (size_t)r.E * sizeof(int2), hipMemcpyDeviceToHost));
+    int rc;
+    if (coords &&
+        (rc = copy_sync(coords, bt->oX + (size_t)r.offV, (size_t)r.V * D * sizeof(double), hipMemcpyDeviceToHost)))
+        return rc;
+    if (signs &&
+        (rc = copy_sync(signs, bt->oSG + r.offSG, (size_t)r.V * r.Wd * sizeof(uint64_t), hipMemcpyDeviceToHost)))
+        return rc;
+    if (edges && (rc = copy_sync(edges, bt->oE + r.offE, (size_t)r.E * sizeof(int2), hipMemcpyDeviceToHost)))
+        return rc;
     return PCX_OK;
 }
 

@@ -243,7 +243,8 @@ int cells_run(const pcx_complex *cx, hipStream_t st, std::vector<int64_t> &count
         if (hctr[CTR_FLAGS] & FLAG_BOUNDS) return fail(PCX_ERR_DEVICE, "internal error: cell table overflow or index out of range");
         if (hctr[CTR_FLAGS] & FLAG_VERIFY) return fail(PCX_ERR_DEVICE, "two cells share a 64-bit hash (retry is not possible)");
         std::vector<int> hc(kChunks);
-        HIPCHK(hipMemcpy(hc.data(), cnt, kChunks * sizeof(int), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(hc.data(), cnt, kChunks * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         const int64_t nn = std::accumulate(hc.begin(), hc.end(), (int64_t)0);
         counts[k + 1] = nn;
         int2 *next = nullptr;

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 
 #include "host.h"
 
@@ -28,6 +29,7 @@ namespace pcx {
 namespace {
 constexpr uint64_t kGraphMaxBytes = uint64_t(1) << 29;     // storage one cached graph may hold (512 MiB)
 constexpr uint64_t kGraphBudget = uint64_t(1) << 32;       // storage all cached graphs may hold (4 GiB)
+constexpr int kGraphBusy = -1000;  // build() could not have the capture gate: try again at a later request
 std::atomic<uint64_t> g_graph_bytes{0};
 }
 
@@ -146,6 +148,9 @@ int build(const pcx_mlp *mlp, const GraphLog &lg, GraphEntry &ge, hipStream_t cs
     HIPCHK(hipMemcpyAsync(dbox, box.data(), 2 * D * 8, hipMemcpyHostToDevice, cs));
     HIPCHK(hipStreamSynchronize(cs));
 
+    // no allocation or free of this library on another thread during the capture
+    std::unique_lock<std::shared_mutex> gate(capture_gate(), std::try_to_lock);
+    if (!gate.owns_lock()) return kGraphBusy;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     const int V0 = 1 << D, E0 = D << (D - 1);
     launch_ctr_init(b.CTR, V0, E0, cs);
@@ -198,8 +203,10 @@ int build(const pcx_mlp *mlp, const GraphLog &lg, GraphEntry &ge, hipStream_t cs
     const hipError_t le = hipGetLastError();
     hipGraph_t graph = nullptr;
     const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    gate.unlock();
     if (le != hipSuccess || ce != hipSuccess || !graph) {
         if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();  // a failed capture leaves no error behind for this thread's later calls
         return fail(PCX_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
     }
     ge.graph = graph;
@@ -255,7 +262,7 @@ int graph_try(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_
         if (gc.log->seen < 2) return kGraphDeclined;
         auto ge = std::make_unique<GraphEntry>();
         if ((rc = build(mlp, *gc.log, *ge, cs))) {
-            gc.log.reset();  // not this network again
+            if (rc != kGraphBusy) gc.log.reset();  // not this network again
             return kGraphDeclined;
         }
         gc.entry = std::move(ge);

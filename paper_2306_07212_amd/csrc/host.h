@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -85,6 +86,15 @@ struct pcx_complex {
 
 
 namespace pcx {
+// A graph capture (graph.hip) on one thread must not overlap this library's
+// device allocations and frees on other threads: those take this gate shared,
+// a capture takes it exclusively (and is skipped when it cannot have it).
+std::shared_mutex &capture_gate();
+// Blocking copy through this thread's own non-blocking stream: the library
+// puts no work on the legacy default stream, which a capture elsewhere in the
+// process would make an error.
+int copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind);
+
 // Device blocks released by finished extractions are kept for reuse, per
 // device and size class, so that repeated extractions of large complexes do
 // not pay for hipMalloc / hipFree of tens of GB each time. pcx_cache_trim()
@@ -120,12 +130,15 @@ struct Pool {
             }
         }
         void *p = nullptr;
-        if (hipMalloc(&p, sz) != hipSuccess) {
-            (void)hipGetLastError();
-            trim();
+        {
+            std::shared_lock<std::shared_mutex> gate(capture_gate());
             if (hipMalloc(&p, sz) != hipSuccess) {
                 (void)hipGetLastError();
-                return nullptr;
+                trim_gated();
+                if (hipMalloc(&p, sz) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return nullptr;
+                }
             }
         }
         std::lock_guard<std::mutex> lk(m);
@@ -143,6 +156,10 @@ struct Pool {
         cached_bytes += it->second.second;
     }
     void trim() {
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
+        trim_gated();
+    }
+    void trim_gated() {
         std::lock_guard<std::mutex> lk(m);
         int cur = 0;
         (void)hipGetDevice(&cur);
@@ -208,7 +225,11 @@ struct Arena {
 constexpr int kGraphDeclined = 1000;
 // pcx_extract without the batch-of-one path for small networks (what a batch's
 // own fallback runs), and that path (batch_api.hip)
-int extract_ordinary(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out);
+// pcx_extract's box extraction; shortcuts: which of a small network's batch of
+// one (kShortcutTiny) and a repeated network's graph (kShortcutGraph) may serve it
+enum { kShortcutTiny = 1, kShortcutGraph = 2 };
+int extract_ordinary(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts, pcx_complex **out,
+                     int shortcuts = 0);
 int tiny_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts &o, pcx_complex **out);
 int graph_try(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts &o, hipStream_t st,
               hipStream_t cs, hipEvent_t t0, hipEvent_t t1, int *pinned, pcx_complex **out);

@@ -310,7 +310,8 @@ extern "C" int pcx_extract_into(const pcx_mlp *mlp, const double *lo, const doub
     StepRec rec[256];
     for (int s0 = 0; s0 < n_steps; s0 += 256) {
         const int n = std::min(256, n_steps - s0);
-        HIPCHK(hipMemcpy(rec, b.REC + s0, n * sizeof(StepRec), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(rec, b.REC + s0, n * sizeof(StepRec), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         for (int k = 0; k < n; ++k) {
             const int64_t K2 = 2 * ((int64_t)rec[k].E1 - rec[k].E0 - rec[k].S);
             total_splits += rec[k].S;

@@ -110,7 +110,8 @@ void worker_loop(pcx_server *s, int w) {
         o.include_output = s->opts.include_output;
         o.stream = s->worker_streams[w];
         pcx_complex *cx = nullptr;
-        const int rc = pcx_extract(j->mlp, j->lo.data(), j->hi.data(), &o, &cx);
+        // no graph capture in the server: it sees few repeats, and its threads run concurrently
+        const int rc = extract_ordinary(j->mlp, j->lo.data(), j->hi.data(), &o, &cx, kShortcutTiny);
         std::string err = rc ? pcx_last_error() : "";
         std::lock_guard<std::mutex> lk(s->mu);
         s->running_large--;

@@ -70,3 +70,61 @@ def test_replays_equal_the_ordinary_path(pcx, monkeypatch, name, incl):
     same(r3, r1)
     m.close()
     mo.close()
+
+
+def test_capture_alongside_other_threads(pcx, monkeypatch):
+    """A capture on one thread while other threads create and free networks,
+    extract (per-step path and batched kernel) and copy results: every call
+    succeeds and every result equals its reference. (The library puts nothing
+    on the legacy default stream, and its allocations and frees wait for a
+    capture in progress.)"""
+    import threading
+    monkeypatch.setenv("PCX_NO_TINY", "1")
+    net = wl.differentiable()
+    box = wl.cube(3)
+    smalls = [wl.he_mlp([2, 16, 16, 1], 300 + i) for i in range(6)]
+    sbox = wl.cube(2)
+    monkeypatch.setenv("PCX_NO_GRAPH", "1")
+    m = pcx.MLP.from_net(net)
+    ref = run(pcx, m, box.lo, box.hi, True)
+    refs = []
+    for n in smalls:
+        ms = pcx.MLP.from_net(n)
+        refs.append(run(pcx, ms, sbox.lo, sbox.hi, False))
+        ms.close()
+    monkeypatch.delenv("PCX_NO_GRAPH")
+    errors, got_graph = [], []
+
+    def repeated():
+        try:
+            for _ in range(6):
+                r = run(pcx, m, box.lo, box.hi, True)
+                same(r, ref)
+                got_graph.append(r[2].from_graph)
+        except Exception as e:  # noqa: BLE001 - reported by the main thread
+            errors.append(("repeated", repr(e)))
+
+    def others(k):
+        try:
+            for it in range(8):
+                i = (k + it) % len(smalls)
+                ms = pcx.MLP.from_net(smalls[i])
+                same(run(pcx, ms, sbox.lo, sbox.hi, False), refs[i])
+                bt = pcx.Batch([ms, ms], [(sbox.lo, sbox.hi)] * 2)
+                for j in range(2):
+                    for x, y in zip(bt.copy(j), refs[i][0]):
+                        assert np.array_equal(x, y)
+                bt.close()
+                ms.close()
+        except Exception as e:  # noqa: BLE001
+            errors.append((f"others {k}", repr(e)))
+
+    ths = [threading.Thread(target=repeated)] + [threading.Thread(target=others, args=(k,)) for k in range(3)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    m.close()
+    assert not errors, errors
+    assert got_graph[:2] == [0, 0]
+    print(f"replays from the graph: {got_graph}", flush=True)
