@@ -73,6 +73,14 @@ typedef struct {
                                without edges; survivors keep their order. The result holds the whole
                                output level set and the cells pruning could not exclude; the per-step
                                counters show the pruned sizes at each layer start. */
+    int32_t verify_pairs;   /* 1: with hash pairing, also compare the two perturbed sign rows of every
+                               pair word by word (Sec. 4.2.2's exact grouping, checked row by row).
+                               Without it a pair is exact for every generic input all the same: a
+                               table entry reached by two different 2-faces gets four arrivals,
+                               which the mutual-record check always catches (the step then goes
+                               to the exact pass). The comparison only adds the detection of two
+                               2-faces each met once (a non-generic input) whose hashes collide.
+                               Sort pairing always compares rows. */
 } pcx_opts;
 
 /* Summary of an extracted complex. */

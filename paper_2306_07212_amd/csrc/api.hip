@@ -720,6 +720,7 @@ int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pc
         g.nx8 = 1;
         g.hkeep = hbits < 64 ? (1ull << hbits) - 1ull : ~0ull;
         g.fbits = fbits;
+        g.verify = o.verify_pairs ? 1 : 0;
         g.Vcap = (int)std::min<size_t>(x.Vcap, INT32_MAX);
         g.Ecap = (int)std::min<size_t>(x.Ecap, INT32_MAX);
         g.Kcap = (int)std::min<size_t>(x.Kcap, INT32_MAX);

@@ -51,6 +51,7 @@ struct BatchArgs {
     unsigned long long capV, capSG, capE;
     BatchResult *res;
     int hbits;         // bits of the 2-face hash kept (64; fewer only in tests)
+    int verify;        // 1: compare the perturbed sign rows of every pair (pcx_opts.verify_pairs)
 };
 
 // bytes of one workgroup arena: vertex region + edges (14 B) + key slots

@@ -105,7 +105,8 @@ __device__ int block_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int 
         int pos = run + wave_off + incl - cnt;
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i)
-            if (own & (1u << i)) emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++, false);
+            if (own & (1u << i))
+                emit_pair(b, g, V0, nslots, base + i, partner[i], (size_t)E1 + pos++, false, g.verify != 0);
         run += total;
         __syncthreads();
     }
@@ -254,6 +255,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             g.par = 0;
             g.hkeep = A.hbits < 64 ? (1ull << A.hbits) - 1ull : ~0ull;
             g.fbits = 64;
+            g.verify = A.verify;
             if (P > 0) {
                 for (uint32_t i = t; i < tsz; i += kThreads) table[i] = 0ull;
                 __syncthreads();

@@ -250,6 +250,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
             const char *v = getenv("PCX_DEBUG_HASH_BITS");
             const int hb = v ? atoi(v) : 64;
             A.hbits = hb >= 1 && hb < 64 ? hb : 64;
+            A.verify = o.verify_pairs ? 1 : 0;
         }
         {
             HIPCHK(hipMemcpyAsync((void *)A.nets, nets.data(), (size_t)n * sizeof(BatchNet), hipMemcpyHostToDevice, st));

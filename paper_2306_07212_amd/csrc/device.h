@@ -201,30 +201,34 @@ __device__ __forceinline__ bool slot_owner(const Bufs &b, const StepGeom &g, int
     return u < p;
 }
 
-// Verifies that key slots sa, sb name the same 2-face (their perturbed sign
-// rows agree on every entry before the current neuron) and appends the
-// intersecting edge between their new vertices. check_hash: also compare the
-// stored 64-bit hashes (the hash table already matched them exactly).
+// Appends the intersecting edge between the new vertices of key slots sa, sb
+// (the same 2-face). check_rows: first verify that their perturbed sign rows
+// agree on every entry before the current neuron; check_hash: also compare the
+// stored 64-bit hashes (the hash table already matched them exactly). preA:
+// words wn .. wn+3 of sa's row, when the caller has loaded them already.
 __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int V0, int nslots, int sa, int sb,
-                                          size_t out, bool check_hash = true) {
+                                          size_t out, bool check_hash = true, bool check_rows = true,
+                                          const uint64_t *preA = nullptr) {
     if ((unsigned)sa >= (unsigned)nslots || (unsigned)sb >= (unsigned)nslots) {
         raise_flag(b.CTR, FLAG_BOUNDS);
         return;
     }
     const int xa = V0 + sa / g.P, xb = V0 + sb / g.P;
-    const uint32_t pa = b.PINFO[sa], pb = b.PINFO[sb];
-    const int wa = (int)(pa >> 8), wb = (int)(pb >> 8);
-    const uint64_t ca = ((pa & 1u) ? 2ull : 1ull) << ((pa >> 1) & 63u);
-    const uint64_t cb = ((pb & 1u) ? 2ull : 1ull) << ((pb >> 1) & 63u);
     const uint64_t *Ra = b.SG + (size_t)xa * g.Wd, *Rb = b.SG + (size_t)xb * g.Wd;
     uint64_t diff = check_hash ? (b.FULL[sa] ^ b.FULL[sb]) : 0ull;
-    // no early exit: the row loads of all words are independent and pipeline
+    if (check_rows) {
+        const uint32_t pa = b.PINFO[sa], pb = b.PINFO[sb];
+        const int wa = (int)(pa >> 8), wb = (int)(pb >> 8);
+        const uint64_t ca = ((pa & 1u) ? 2ull : 1ull) << ((pa >> 1) & 63u);
+        const uint64_t cb = ((pb & 1u) ? 2ull : 1ull) << ((pb >> 1) & 63u);
+        // no early exit: the row loads of all words are independent and pipeline
 #pragma unroll 8
-    for (int w = 0; w <= g.wn; ++w) {
-        const uint64_t lt = lt_mask(w, g.wn, g.bn);
-        const uint64_t fa = (Ra[w] & lt) | (w == wa ? ca : 0ull);
-        const uint64_t fb = (Rb[w] & lt) | (w == wb ? cb : 0ull);
-        diff |= fa ^ fb;
+        for (int w = 0; w <= g.wn; ++w) {
+            const uint64_t lt = lt_mask(w, g.wn, g.bn);
+            const uint64_t fa = (Ra[w] & lt) | (w == wa ? ca : 0ull);
+            const uint64_t fb = (Rb[w] & lt) | (w == wb ? cb : 0ull);
+            diff |= fa ^ fb;
+        }
     }
     if (diff) raise_pair_flag(b.CTR, FLAG_VERIFY, g.step);
     // first crossing after the neuron: four words per round, loaded together
@@ -234,7 +238,8 @@ __device__ __forceinline__ void emit_pair(const Bufs &b, const StepGeom &g, int 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int w = w0 + i;
-            x[i] = w < g.lw1 ? (Ra[w] ^ Rb[w]) & gt_mask(w, g.wn, g.bn, g.lw1) : 0ull;
+            const uint64_t a = preA && w0 == g.wn ? preA[i] : (w < g.lw1 ? Ra[w] : 0ull);
+            x[i] = w < g.lw1 ? (a ^ Rb[w]) & gt_mask(w, g.wn, g.bn, g.lw1) : 0ull;
         }
 #pragma unroll
         for (int i = 3; i >= 0; --i)

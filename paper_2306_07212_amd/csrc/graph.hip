@@ -71,7 +71,8 @@ namespace {
 bool eligible(const pcx_opts &o) {
     const char *off = getenv("PCX_NO_GRAPH");
     if (off && off[0] == '1') return false;
-    return o.pairing == PCX_PAIR_HASH && !o.prune && !o.record_tape && o.timing == 0 && o.max_bytes == 0;
+    return o.pairing == PCX_PAIR_HASH && !o.prune && !o.record_tape && o.timing == 0 && o.max_bytes == 0 &&
+           !o.verify_pairs;
 }
 
 bool same_key(const GraphLog &g, int D, const double *lo, const double *hi, int incl) {

@@ -93,6 +93,7 @@ struct StepGeom {
     int Vcap, Ecap, Kcap;  // storage the step may fill (else FLAG_CAPACITY)
     uint64_t hkeep;  // mask of the 2-face hash bits kept (all; fewer only to test the exact pass)
     int fbits;       // bits of the exact pass's sort key kept (64; fewer only to test its grouping)
+    int verify;      // 1: also compare the two perturbed sign rows of every hash-table pair word by word
 };
 
 // Log of one neuron step, written by its last kernel: counts at its start, its

@@ -805,19 +805,21 @@ void launch_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int nslots, c
 //
 // The split recorded every pair as it found it (the second arrival at a
 // 2-face). Two passes over the key slots emit the pairs in the order of their
-// owner slots: the first checks every valid slot's record (fresh and mutual)
-// and counts the owners of each workgroup's chunk of slots; the second adds
-// the counts of the chunks before its own and ranks the owners inside the
-// chunk by wave ballots. The edge list is therefore the same on every run and
-// whatever the launch shapes.
+// owner slots (the smaller slot of a pair): the first counts the owners of each
+// workgroup's chunk of slots from the slots' own records; the second adds the
+// counts of the chunks before its own, ranks the owners inside the chunk by
+// wave ballots, and checks every slot: a fresh record must be mutual, and a
+// valid slot must have one (a failure sends the step to the exact pass). The
+// edge list is therefore the same on every run and whatever the launch shapes.
 __device__ __forceinline__ void pair_chunk(int n, int &c0, int &c1) {
     const int per = ((n + (int)gridDim.x - 1) / (int)gridDim.x + kPairItems - 1) / kPairItems * kPairItems;
     c0 = min(n, (int)blockIdx.x * per);
     c1 = min(n, c0 + per);
 }
 
-// Pass 1: check every valid key slot's partner record, count the owners of
-// each chunk (SELCNT).
+// Pass 1: owners of each chunk (SELCNT), from one coalesced read of the
+// records (a slot whose fresh record names a larger slot). It also empties the
+// previous step's table, which no kernel reads any more, for the next step.
 __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g) {
     __shared__ int s_w[kThreads / 64];
     // this step's split must not have failed its pairing (else the exact pass redoes it)
@@ -825,11 +827,12 @@ __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g) {
     const int S = b.CTR[CTR_S], nslots = S * g.P;
     int c0, c1;
     pair_chunk(nslots, c0, c1);
-    int cnt = 0;
-    for (int u = c0 + (int)threadIdx.x; u < c1; u += kThreads) {
-        int partner;
-        cnt += slot_owner(b, g, u, nslots, partner);
+    if (g.HTo) {
+        const uint32_t clear_n = (uint32_t)b.CTR[CTR_TUSED + (g.par ^ 1)];
+        for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < clear_n; i += gridDim.x * kThreads) g.HTo[i] = 0ull;
     }
+    int cnt = 0;
+    for (int u = c0 + (int)threadIdx.x; u < c1; u += kThreads) cnt += slot_partner(b, g, u, nslots) > u;
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = cnt;
     __syncthreads();
@@ -840,7 +843,8 @@ __global__ __launch_bounds__(kThreads) void k_hpair_count(Bufs b, StepGeom g) {
     }
 }
 
-// Pass 2: owners in slot order append their intersecting edges.
+// Pass 2: every slot's record checked; owners in slot order append their
+// intersecting edges.
 __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_base;
@@ -848,17 +852,33 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     const int S = b.CTR[CTR_S], nslots = S * g.P;
     const int V0 = b.CTR[CTR_V + g.par], E0 = b.CTR[CTR_E + g.par], E1 = E0 + S;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    // the previous step's table is no longer read: make it empty for the next step
-    if (g.HTo) {
-        const uint32_t clear_n = (uint32_t)b.CTR[CTR_TUSED + (g.par ^ 1)];
-        for (uint32_t i = blockIdx.x * kThreads + t; i < clear_n; i += gridDim.x * kThreads) g.HTo[i] = 0ull;
-    }
     int c0, c1;
     pair_chunk(nslots, c0, c1);
-    int pre = 0;
-    for (int i = t; i < (int)blockIdx.x; i += kThreads) pre += b.SELCNT[i];
-    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
-    if (lane == 0) s_w[wave] = pre;
+    // one slot per thread: an owner's edge is a chain of dependent row loads,
+    // so owners are spread over as many threads as possible. A slot's record,
+    // its partner's, and its row words from the neuron on (where an owner's
+    // first-crossing search starts) are loaded together.
+    int partner = -1;
+    uint64_t pre[4];
+    auto load_slot = [&](int u) {
+        partner = -1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pre[i] = 0ull;
+        if (u >= c1) return;
+        const uint64_t *Ra = b.SG + (size_t)(V0 + u / g.P) * g.Wd;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (g.wn + i < g.lw1) pre[i] = Ra[g.wn + i];
+        partner = slot_partner(b, g, u, nslots);
+        // a fresh record must be returned by the partner's; a valid slot must have one
+        if (partner >= 0 ? slot_partner(b, g, partner, nslots) != u : b.PINFO[u] != kNoInfo)
+            raise_pair_flag(b.CTR, FLAG_RUN, g.step);
+    };
+    load_slot(c0 + t);  // in flight while the chunk's offset is summed
+    int pre_cnt = 0;
+    for (int i = t; i < (int)blockIdx.x; i += kThreads) pre_cnt += b.SELCNT[i];
+    for (int o = 32; o > 0; o >>= 1) pre_cnt += __shfl_xor(pre_cnt, o, 64);
+    if (lane == 0) s_w[wave] = pre_cnt;
     __syncthreads();
     if (t == 0) {
         int x = 0;
@@ -875,12 +895,9 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
     }
     __syncthreads();
     int run = s_base;
-    // one slot per thread: an owner's edge is a chain of dependent row loads,
-    // so owners are spread over as many threads as possible
     for (int tb = c0; tb < c1; tb += kThreads) {
         const int u = tb + t;
-        // (pass 1 checked every record: a valid slot's partner is fresh and mutual)
-        const int partner = u < c1 && b.PINFO[u] != kNoInfo ? slot_partner(b, g, u, nslots) : -1;
+        if (tb != c0) load_slot(u);
         const bool own = partner > u;
         const uint64_t m = __ballot(own);
         __syncthreads();  // s_w of the previous round has been read
@@ -895,7 +912,7 @@ __global__ __launch_bounds__(kThreads) void k_hpair_emit(Bufs b, StepGeom g) {
         }
         if (own) {
             const int pos = run + wave_off + __popcll(m & ((1ull << lane) - 1ull));
-            emit_pair(b, g, V0, nslots, u, partner, (size_t)E1 + pos, false);
+            emit_pair(b, g, V0, nslots, u, partner, (size_t)E1 + pos, false, g.verify != 0, pre);
         }
         run += total;
     }

@@ -211,6 +211,7 @@ extern "C" int pcx_extract_into(const pcx_mlp *mlp, const double *lo, const doub
         g.nx8 = 1;
         g.hkeep = ~0ull;
         g.fbits = 64;
+        g.verify = o.verify_pairs ? 1 : 0;
         g.Vcap = (int)Vcap;
         g.Ecap = (int)Ecap;
         g.Kcap = (int)std::min<size_t>(Kcap, INT32_MAX);

@@ -55,7 +55,7 @@ class PcxError(RuntimeError):
 class _Opts(C.Structure):
     _fields_ = [("include_output", C.c_int32), ("timing", C.c_int32), ("pairing", C.c_int32),
                 ("record_tape", C.c_int32), ("max_bytes", C.c_uint64), ("stream", C.c_void_p),
-                ("batch_wg_per_cu", C.c_int32), ("prune", C.c_int32)]
+                ("batch_wg_per_cu", C.c_int32), ("prune", C.c_int32), ("verify_pairs", C.c_int32)]
 
 
 class _BatchStats(C.Structure):
@@ -338,16 +338,18 @@ def backward(mlp: MLP, cx: Complex, grad_coords_ptr: int, gW_ptrs, gb_ptrs, prec
 
 
 def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=None,
-            max_bytes: int = 0, pairing: str = "hash", record_tape: bool = False, prune: bool = False) -> Complex:
+            max_bytes: int = 0, pairing: str = "hash", record_tape: bool = False, prune: bool = False,
+            verify_pairs: bool = False) -> Complex:
     """``pcx_extract``: edge subdivision of the box [lo, hi] by every subdivided neuron.
-    ``prune`` (with ``include_output``): pruning during subdivision for the output's level set."""
+    ``prune`` (with ``include_output``): pruning during subdivision for the output's level set.
+    ``verify_pairs``: compare the perturbed sign rows of every hash-table pair too."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
     tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
     o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream, 0,
-              int(bool(prune)))
+              int(bool(prune)), int(bool(verify_pairs)))
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract(mlp._h, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD), C.byref(o), C.byref(h)))
@@ -355,7 +357,7 @@ def extract(mlp: MLP, lo, hi, include_output: bool = False, timing=0, stream=Non
 
 
 def extract_into(mlp: MLP, lo, hi, coords_ptr: int, signs_ptr: int, edges_ptr: int, max_vertices: int,
-                 max_edges: int, include_output: bool = False, stream=None):
+                 max_edges: int, include_output: bool = False, stream=None, verify_pairs: bool = False):
     """``pcx_extract_into``: the extraction written into caller-allocated device
     buffers (raw pointers), with no device allocation by the library. Returns
     (Info, per-step counters [n_steps, 4] int64)."""
@@ -363,7 +365,7 @@ def extract_into(mlp: MLP, lo, hi, coords_ptr: int, signs_ptr: int, edges_ptr: i
     hi = np.ascontiguousarray(hi, np.float64)
     if lo.shape != (mlp.D,) or hi.shape != (mlp.D,):
         raise ValueError("lo and hi must have D entries")
-    o = _Opts(int(bool(include_output)), 0, 0, 0, 0, stream, 0, 0)
+    o = _Opts(int(bool(include_output)), 0, 0, 0, 0, stream, 0, 0, int(bool(verify_pairs)))
     L = len(mlp.widths) - 1
     n_steps = sum(mlp.widths[1:L + 1 if include_output else L])
     steps = np.zeros((max(1, n_steps), 4), np.int64)
@@ -378,7 +380,8 @@ def extract_into(mlp: MLP, lo, hi, coords_ptr: int, signs_ptr: int, edges_ptr: i
 
 
 def extract_simplex(mlp: MLP, corners, include_output: bool = False, timing=0, stream=None, max_bytes: int = 0,
-                    pairing: str = "hash", record_tape: bool = False, prune: bool = False) -> Complex:
+                    pairing: str = "hash", record_tape: bool = False, prune: bool = False,
+                    verify_pairs: bool = False) -> Complex:
     """``pcx_extract_simplex``: edge subdivision of the simplex with the given D + 1
     corners (rows); sign entries 0..D are the barycentric coordinates."""
     P = np.ascontiguousarray(corners, np.float64)
@@ -386,7 +389,7 @@ def extract_simplex(mlp: MLP, corners, include_output: bool = False, timing=0, s
         raise ValueError("corners must be (D + 1) x D")
     tm = timing if isinstance(timing, int) and not isinstance(timing, bool) else timing_mask(timing)
     o = _Opts(int(bool(include_output)), int(tm), PAIRING[pairing], int(bool(record_tape)), int(max_bytes), stream, 0,
-              int(bool(prune)))
+              int(bool(prune)), int(bool(verify_pairs)))
     h = C.c_void_p()
     PD = C.POINTER(C.c_double)
     _check(_lib.pcx_extract_simplex(mlp._h, P.ctypes.data_as(PD), C.byref(o), C.byref(h)))
@@ -420,12 +423,13 @@ class Batch:
     """``pcx_extract_batch``: many networks in one persistent launch."""
 
     def __init__(self, mlps, boxes, include_output: bool = False, wg_per_cu: int = 0, stream=None,
-                 max_bytes: int = 0):
+                 max_bytes: int = 0, verify_pairs: bool = False):
         self.mlps = list(mlps)
         self.include_output = include_output
         arr, lo, hi = _batch_args(self.mlps, boxes)
         PD = C.POINTER(C.c_double)
-        o = _Opts(int(bool(include_output)), 0, 0, 0, int(max_bytes), stream, int(wg_per_cu), 0)
+        o = _Opts(int(bool(include_output)), 0, 0, 0, int(max_bytes), stream, int(wg_per_cu), 0,
+                  int(bool(verify_pairs)))
         h = C.c_void_p()
         _check(_lib.pcx_extract_batch(len(self.mlps), arr, lo.ctypes.data_as(PD), hi.ctypes.data_as(PD),
                                       C.byref(o), C.byref(h)))

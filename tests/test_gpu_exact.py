@@ -114,3 +114,45 @@ def test_exact_pass_on_the_large_workload_steps(pcx, monkeypatch):
     assert info.exact_steps > 100
     for a, b in zip(got, ref):
         assert a.shape == b.shape and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("widths,seed,incl", NETS[:4])
+def test_row_verification_changes_nothing(pcx, monkeypatch, widths, seed, incl):
+    """verify_pairs (every hash-table pair's perturbed sign rows compared word
+    by word) gives the same complex as the default, which relies on the
+    mutual-record check; with collisions forced, both go through the exact
+    pass alike."""
+    net = wl.he_mlp(widths, seed)
+    box = wl.cube(net.D)
+    m = pcx.MLP.from_net(net)
+
+    def go(verify):
+        cx = pcx.extract(m, box.lo, box.hi, include_output=incl, verify_pairs=verify)
+        out, info, steps = cx.copy(), cx.info(), cx.steps()
+        cx.close()
+        return out, info, steps
+
+    monkeypatch.setenv("PCX_NO_TINY", "1")
+    monkeypatch.setenv("PCX_NO_GRAPH", "1")
+    a, ia, sa = go(False)
+    b, ib, sb = go(True)
+    assert ia.exact_steps == ib.exact_steps == 0
+    assert all(np.array_equal(x, y) for x, y in zip(a, b)) and np.array_equal(sa, sb)
+    monkeypatch.setenv("PCX_DEBUG_HASH_BITS", "2")
+    c, ic, _ = go(False)
+    d, id_, _ = go(True)
+    assert ic.exact_steps > 0 and id_.exact_steps > 0
+    assert all(np.array_equal(x, y) for x, y in zip(c, a)) and all(np.array_equal(x, y) for x, y in zip(d, a))
+    monkeypatch.delenv("PCX_DEBUG_HASH_BITS")
+    # the batched kernel, with and without the row comparison
+    nets = [wl.he_mlp([2, w, w, 1], 600 + w) for w in (8, 16, 24, 32)]
+    mlps = [pcx.MLP.from_net(n) for n in nets]
+    boxes = [(wl.cube(2).lo, wl.cube(2).hi)] * len(nets)
+    b0, b1 = pcx.Batch(mlps, boxes), pcx.Batch(mlps, boxes, verify_pairs=True)
+    for i in range(len(nets)):
+        assert all(np.array_equal(x, y) for x, y in zip(b0.copy(i), b1.copy(i)))
+    b0.close()
+    b1.close()
+    for x in mlps:
+        x.close()
+    m.close()
