@@ -759,6 +759,17 @@ def main():
             cpl = by["split"] / per_ext_launches
             roof["carried_columns"] = {"bytes_per_launch": cpl, "achieved": cpl / avg_launch_s / 1e9,
                                        "frac": cpl / avg_launch_s / 1e9 / HBM_PEAK_GBS}
+            # the per-layer sums the count needs: bytes = sum over layers of
+            # (3 (8D + 8 Wd) + 12) sum_S + 24 sum_S_Ln + 12 sum_K
+            layers, Wd_ = layer_table(net.widths, incl)
+            terms, s0 = [], 0
+            for ly in layers:
+                blk = np.asarray(steps[s0:s0 + ly["N"]], np.float64)
+                Ln = ly["N"] - 1 - np.arange(len(blk))
+                terms.append({"N": ly["N"], "sum_S": int(blk[:, 2].sum()), "sum_S_Ln": int((blk[:, 2] * Ln).sum()),
+                              "sum_K": int(blk[:, 3].sum())})
+                s0 += ly["N"]
+            roof["scope_terms"] = {"D": D, "Wd": Wd_, "layers": terms}
     # every family, from the per-family medians of the R extractions with all families timed
     fam_roof = {}
     for f in FAMILIES:
