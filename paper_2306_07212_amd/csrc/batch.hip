@@ -249,6 +249,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
             g.pair_mode = PAIR_HASH;
             g.HT = table;
             g.hmask = tsz - 1;
+            g.sbits = kSlotBits;  // (a network's steps have far fewer key slots than 2^24)
             g.zlo = 0;
             g.nx8 = 0;
             g.step = step;

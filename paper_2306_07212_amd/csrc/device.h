@@ -164,14 +164,15 @@ __device__ __forceinline__ void record_pair(const Bufs &b, const StepGeom &g, ui
 }
 
 __device__ __forceinline__ void hash_insert(const Bufs &b, const StepGeom &g, uint64_t H, uint32_t u, int nslots) {
-    const unsigned long long key = (H >> 25) & kKeyMask;
-    const unsigned long long mine = (key << kSlotBits) | (unsigned long long)(u + 1);
+    const int sb = g.sbits;  // (the key: the hash bits above 25 that fit beside the slot)
+    const unsigned long long key = (H >> 25) & ((1ull << (64 - sb)) - 1ull);
+    const unsigned long long mine = (key << sb) | (unsigned long long)(u + 1);
     uint32_t h = (uint32_t)H & g.hmask;
     for (uint32_t probe = 0; probe <= g.hmask; ++probe) {
         const unsigned long long old = atomicCAS(&g.HT[h], 0ull, mine);
         if (old == 0ull) return;  // first arrival: the second records the pair
-        if ((old >> kSlotBits) == key) {
-            record_pair(b, g, u, (uint32_t)(old & kSlotMask) - 1u, nslots);
+        if ((old >> sb) == key) {
+            record_pair(b, g, u, (uint32_t)(old & ((1ull << sb) - 1ull)) - 1u, nslots);
             return;
         }
         h = (h + 1) & g.hmask;

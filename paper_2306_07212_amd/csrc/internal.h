@@ -61,10 +61,15 @@ constexpr int kPairFlags = FLAG_RUN | FLAG_VERIFY | FLAG_BIGSTEP;
 // publishes its key and its key slot together: bits 63..24 = 40 bits of the
 // face hash, bits 23..0 = 1 + the key slot. The second arrival finds its
 // partner's slot in the value its own CAS returns.
-constexpr int kSlotBits = 24;
-constexpr uint32_t kMaxHashSlots = (1u << kSlotBits) - 2;  // key slots a step may have on the table path
-constexpr unsigned long long kKeyMask = (1ull << 40) - 1;
-constexpr unsigned long long kSlotMask = (1ull << kSlotBits) - 1;
+constexpr int kSlotBits = 24;                              // narrowest slot field of a table word
+constexpr uint32_t kMaxHashSlots = (1u << 29) - 2;         // key slots a step may have on the table path
+// Width of the slot field of a step's table words (the key takes the other
+// bits): at least kSlotBits, and enough to name n slots plus the empty value.
+__host__ __device__ inline int slot_bits(int n) {
+    int b = kSlotBits;
+    while ((1ll << b) < (long long)n + 2) ++b;
+    return b;
+}
 // Partner record of a key slot, written by the second arrival at its 2-face
 // (or by the exact pass) for both slots of the pair: high 32 bits = 1 + the
 // step that wrote it, low 32 bits = 1 + the other slot. The pair's owner is
@@ -94,6 +99,7 @@ struct StepGeom {
     uint64_t hkeep;  // mask of the 2-face hash bits kept (all; fewer only to test the exact pass)
     int fbits;       // bits of the exact pass's sort key kept (64; fewer only to test its grouping)
     int verify;      // 1: also compare the two perturbed sign rows of every hash-table pair word by word
+    int sbits;       // slot field width of this step's table words (slot_bits of its key slots)
 };
 
 // Log of one neuron step, written by its last kernel: counts at its start, its

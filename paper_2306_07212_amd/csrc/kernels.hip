@@ -536,7 +536,10 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
         // more key slots than a table word can name: the exact pass pairs this step
         if (g.pair_mode == PAIR_HASH && (uint32_t)nslots > kMaxHashSlots) raise_pair_flag(b.CTR, FLAG_BIGSTEP, g.step);
     }
-    if (g.pair_mode == PAIR_HASH) g.hmask = (uint32_t)nslots <= kMaxHashSlots ? table_size(nslots) - 1u : 0u;
+    if (g.pair_mode == PAIR_HASH) {
+        g.hmask = (uint32_t)nslots <= kMaxHashSlots ? table_size(nslots) - 1u : 0u;
+        g.sbits = slot_bits(nslots);
+    }
     constexpr int groups = kThreads / G;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;

@@ -72,8 +72,10 @@ def assert_same_complex(A, B, coord_tol=1e-10):
     assert err <= coord_tol, f"coordinates differ by {err}"
 
 
-def check_invariants(net, lo, hi, X, S, edges, include_output=False, zero_tol=1e-9, full=True):
-    """Properties that hold for the 1-skeleton of any generic instance."""
+def check_invariants(net, lo, hi, X, S, edges, include_output=False, zero_tol=1e-9, full=True, sample=None):
+    """Properties that hold for the 1-skeleton of any generic instance. sample:
+    run the forward-pass checks on that many random vertices and edges only
+    (the combinatorial checks always cover everything)."""
     V, M = S.shape
     D = X.shape[1]
     edges = np.asarray(edges, np.int64)
@@ -107,14 +109,23 @@ def check_invariants(net, lo, hi, X, S, edges, include_output=False, zero_tol=1e
     assert 2 * len(edges) == np.sum(2 * D - zbox)
     if not full:
         return
+    X_full, S_full = X, S
+    if sample is not None:
+        rng = np.random.default_rng(0)
+        vi = rng.choice(V, size=min(sample, V), replace=False)
+        X, S = X[vi], S[vi]
+        ei = rng.choice(len(a), size=min(sample, len(a)), replace=False)
+        Sa, Sb, Xa, Xb = S_full[a[ei]], S_full[b[ei]], X_full[a[ei]], X_full[b[ei]]
+    else:
+        Sa, Sb, Xa, Xb = S_full[a], S_full[b], X_full[a], X_full[b]
     # validation of Sec. 5.1.1: zero entries evaluate to ~0, signs agree elsewhere
     vals = entry_values(net, lo, hi, X, include_output)
     assert np.all(np.abs(vals[S == 0]) < zero_tol), f"max |z| at zeros {np.abs(vals[S == 0]).max()}"
     nz = S != 0
     assert np.all(np.sign(vals[nz]) == S[nz]), "forward-pass sign differs from sign-vector"
     # midpoint of each edge lies in the edge's cell: sign = join
-    jn = np.where(S[a] == 0, S[b], S[a])
-    mid = 0.5 * (X[a] + X[b])
+    jn = np.where(Sa == 0, Sb, Sa)
+    mid = 0.5 * (Xa + Xb)
     mv = entry_values(net, lo, hi, mid, include_output)
     assert np.all(np.abs(mv[jn == 0]) < 1e-7), "edge leaves a hyperplane it should lie on"
     assert np.all(np.sign(mv[jn != 0]) == jn[jn != 0]), "edge midpoint outside its cell"

@@ -156,3 +156,25 @@ def test_row_verification_changes_nothing(pcx, monkeypatch, widths, seed, incl):
     for x in mlps:
         x.close()
     m.close()
+
+
+def test_step_with_more_key_slots_than_24_bits_name(pcx):
+    """6-32-32-1 on [-1,1]^6 (57M vertices): its largest steps have more than
+    2^24 key slots, so the table words give the slot field more bits (and the
+    key fewer); no step may fall back to the exact pass, and the per-step
+    counters equal those of the sort pairing, which compares sign rows."""
+    net = wl.he_mlp([6, 32, 32, 1], 6)
+    box = wl.cube(6)
+    m = pcx.MLP.from_net(net)
+    cx = pcx.extract(m, box.lo, box.hi)
+    info, steps = cx.info(), cx.steps()
+    cx.close()
+    print(f"[exact] 6-32-32-1: V={info.V} E={info.E}, largest step {int(steps[:, 3].max())} paired key slots, "
+          f"{info.exact_steps} exact steps", flush=True)
+    assert int(steps[:, 2].max()) * 10 > (1 << 24)
+    assert info.exact_steps == 0
+    cx = pcx.extract(m, box.lo, box.hi, pairing="sort")
+    s2 = cx.steps()
+    cx.close()
+    m.close()
+    assert np.array_equal(steps, s2)

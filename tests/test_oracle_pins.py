@@ -143,7 +143,9 @@ def test_invariants_differentiable_workload(oracle_lib):
     net = wl.differentiable()
     box = wl.cube(3)
     r = oracle_lib.extract(net, box.lo, box.hi, include_output=True)
-    check_invariants(net, box.lo, box.hi, r.X, r.S, r.edges, include_output=True)
+    # forward-pass checks on 200K vertices and 200K edges (the rest of the
+    # checks on all 0.67M vertices and 2.0M edges)
+    check_invariants(net, box.lo, box.hi, r.X, r.S, r.edges, include_output=True, sample=200000)
     assert r.min_margin > 1e-12
 
 
