@@ -64,7 +64,6 @@ def algorithmic_cost(widths, steps, include_output=False):
         by["next"] += E0 * (8.0 + 2 * 8.0 * nw + 2.0)
         for j, st in enumerate(steps[s0:s0 + N]):
             V, E, S, Kv = (float(v) for v in st)
-            wn = ly["lw0"] + j // 32  # face sign-vectors span words 0..wn
             by["select"] += 2.0 * E + 4.0 * S
             # split: read SPL id, edge, the two endpoint values at neuron j, two rows (coords, carried
             # pre-activations, signs), write one row, two edges, two next-crossings, and 2-face keys
@@ -74,9 +73,10 @@ def algorithmic_cost(widths, steps, include_output=False):
             by["split"] += S * (4 + 8 + 16 + 3 * (8.0 * D + 8.0 * Nc + 8.0 * Wd) + 16 + 4) + 4.0 * S * P + 12.0 * Kv
             # sort: linear grouping reads and writes each (key, slot) pair once
             by["sort"] += 16.0 * S * P
-            # pair: per key its (key, slot) or table entry, hash and perturbed entry; per pair two face
-            # rows, one edge, one next crossing
-            by["pair"] += Kv * (8.0 + 12.0) + (Kv / 2) * (2 * 8.0 * (wn + 1) + 8 + 2)
+            # pair: per key slot its 12-byte key read (the scope table's figure); per pair one edge,
+            # one next crossing and the sign word at the neuron of both new vertices (the first
+            # crossing search); the optional row comparison (2 * 8 (wn + 1) per pair) is not counted
+            by["pair"] += Kv * 12.0 + (Kv / 2) * (8.0 + 1.0 + 2 * 8.0)
         s0 += N
     return by, flops
 
