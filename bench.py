@@ -781,6 +781,10 @@ def main():
         if f == "gemm":
             fam_roof[f]["TFLOP_per_s"] = flops / s_ / 1e12
             fam_roof[f]["mfma_frac"] = flops / s_ / 1e12 / FP64_PEAK_TFLOPS
+        if f == "pair":
+            fam_roof[f]["note"] = ("12 B per key slot and 25 B per pair (edge, next crossing, one sign word of each "
+                                   "new vertex); two launches per neuron of a few microseconds each, so latency, "
+                                   "not bytes, bounds it")
     sub_ms = sum(med_ms[f] for f in ("next", "select", "split", "sort", "pair"))
     subdivision = {"bytes": b8_total, "ms": sub_ms, "GB_per_s": b8_total / (sub_ms / 1e3) / 1e9,
                    "hbm_frac": b8_total / (sub_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
