@@ -96,7 +96,7 @@ typedef struct {
     uint64_t peak_bytes;    /* device bytes held at the peak of the extraction */
     double time_ms;         /* device time of the extraction (HIP events, weights resident) */
     int32_t exact_steps;    /* steps whose 2-face pairing was redone by the exact pass (a hash
-                               collision, or a step with more than 2^24 - 2 key slots); the result
+                               collision, or a step with more than 2^29 - 2 key slots); the result
                                is the same complex either way */
     int32_t from_graph;     /* 1: a repeat of the network's last extraction (same box and options),
                                replayed from its captured HIP graph (the same complex) */
@@ -120,7 +120,12 @@ void pcx_mlp_free(pcx_mlp *mlp);
  * whole kernel sequence in a HIP graph (storage of its own, up to 512 MiB per
  * network and 4 GiB over all networks, held until pcx_mlp_free) and later ones
  * replay it (PCX_NO_GRAPH=1 in the environment turns this off). A replay whose
- * steps differ from the log is discarded and the ordinary path runs. */
+ * steps differ from the log is discarded and the ordinary path runs. A capture
+ * waits for no other call: while another thread of the process is inside a
+ * device allocation or free of this library it is skipped until a later
+ * request. A network whose predicted complex has at most 1024 vertices runs as
+ * a batch of one instead (one launch of the batched kernel, the same complex;
+ * PCX_NO_TINY=1 turns this off). */
 int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts,
                 pcx_complex **out);
 
@@ -195,8 +200,10 @@ void pcx_complex_free(pcx_complex *cx);
  * numbering, bit-identical values); a workgroup runs one network at a time
  * from a largest-first queue. Networks that exceed the batched kernel's limits
  * (D > 8, more than 8 layers, a layer wider than 256, or a predicted complex
- * above 65536 vertices), or its per-workgroup arena, are extracted on the
- * per-step path inside the same call. mlps[i] and the boxes lo/hi (the D_i
+ * above 65536 vertices), or its per-workgroup arena, and networks whose
+ * 2-face pairing failed inside the kernel (a hash collision: the per-step path
+ * has the exact pass) are extracted on the per-step path inside the same call.
+ * mlps[i] and the boxes lo/hi (the D_i
  * coordinates of network i, concatenated over i; host memory) are read during
  * the call. opts->include_output applies to every network. */
 typedef struct pcx_batch pcx_batch;
@@ -317,7 +324,9 @@ int pcx_extract_into(const pcx_mlp *mlp, const double *lo, const double *hi, con
  * arithmetic of the reverse pass: PCX_F64 or PCX_F32 (results still FP64).
  * Each new vertex x0 = x_p + t (x_q - x_p), t = z_p / (z_p - z_q) of its
  * splitting edge (Sec. 4.2.1) is differentiated exactly as the forward pass
- * computed it; the call returns when the gradients are complete. */
+ * computed it; every vertex sums its children's contributions in child order
+ * (no atomics), so the gradients are bit-identical from run to run. The call
+ * returns when the gradients are complete. */
 #define PCX_F64 0
 #define PCX_F32 1
 int pcx_backward(const pcx_mlp *mlp, const pcx_complex *cx, const double *grad_coords, double *const *gW,
