@@ -112,7 +112,8 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
 void pcx_mlp_free(pcx_mlp *mlp);
 
 /* Edge subdivision of the box [lo, hi] (D host doubles each, lo < hi) by every
- * subdivided neuron of mlp, in layer order (Sec. 4.2). On success *out owns
+ * subdivided neuron of mlp, in layer order (Sec. 4.2); a subdivided layer may
+ * have at most 256 neurons (else PCX_ERR_INVALID). On success *out owns
  * the complex on the device. On error *out is NULL. Work is queued on
  * opts->stream; the call returns when the complex is complete. A network keeps
  * the step log of its last extraction (hash pairing, no prune, tape, timing or

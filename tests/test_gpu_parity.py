@@ -250,3 +250,42 @@ def test_kernel_timing_leaves_the_complex_unchanged(pcx, pairing):
                 assert times["gemm"][1] >= 2 and times["gemm"][0] > 0.0
     finally:
         m.close()
+
+
+def _corner_net():
+    """16 inputs (the box entries fill sign word 0): two hyperplanes cutting
+    the corners (1,...,1) and (1,...,1,-1) of [-1,1]^16, then one neuron
+    h1 + h2 = 0.2 inside the first corner."""
+    w1 = np.ones((2, 16))
+    w1[1, 15] = -1.0
+    return wl.Net([16, 2, 1, 1], [w1, np.array([[1.0, 1.0]]), np.array([[1.0]])],
+                  [np.array([-15.5, -15.3]), np.array([-0.2]), np.array([0.0])])
+
+
+@pytest.mark.parametrize("pairing", ["hash", "sort"])
+def test_sixteen_inputs_fill_the_box_word(oracle_lib, pcx, pairing):
+    """D = 16, the largest input dimension: 65,536 corners, 524,288 box edges,
+    30 key slots per split (2-faces at a box corner), every box entry in word 0."""
+    net = _corner_net()
+    box = wl.cube(16)
+    m = pcx.MLP.from_net(net)
+    cx = pcx.extract(m, box.lo, box.hi, pairing=pairing)
+    X, SG, Ed = cx.copy()
+    steps = cx.steps()
+    cx.close()
+    m.close()
+    r = oracle_lib.extract(net, box.lo, box.hi)
+    assert np.array_equal(steps, r.steps)
+    assert_same_complex((X, unpack_signs(SG, net.widths), Ed), (r.X, r.S, r.edges))
+
+
+def test_empty_batch_and_idle_server(pcx):
+    """A batch of no networks and a server that never gets a request."""
+    bt = pcx.Batch([], [])
+    st = bt.stats()
+    assert st.n == 0 and st.total_V == 0 and st.fallbacks == 0
+    bt.close()
+    srv = pcx.Server()
+    s = srv.stats()
+    assert s["completed"] == 0
+    srv.close()
