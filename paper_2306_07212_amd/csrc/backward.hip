@@ -132,29 +132,73 @@ __global__ __launch_bounds__(kThreads) void k_bwd_parent(const double *__restric
     }
 }
 
-// Partial sums of dW[c][k] = sum_v gz[v][c] h[v][k] and db[c] = sum_v gz[v][c]
-// over a chunk of the vertices present at the layer start (blockIdx.y).
+// Partial sums of the weight and bias gradients over one chunk of vertices:
+// part[chunk][c][k] = sum_v gz[v][c] h[v][k], h = ReLU of the previous layer's
+// pre-activations (the coordinates for layer 1), and k == K is the bias
+// (h = 1). A workgroup takes a 64 x 64 tile of the (c, k) entries and its
+// chunk, stages 32 vertices' gz and h values of the tile through LDS at a time,
+// and each thread accumulates 4 x 4 entries. Every entry sums its chunk's
+// vertices in order, one fused multiply-add each, and k_bwd_wreduce adds the
+// chunks in order: the gradients are the same bits on every run.
+constexpr int kWgTile = 64, kWgRows = 32;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_wgrad(const T *__restrict__ gz, int ZS, const double *__restrict__ hin,
-                                                         int hstride, int relu, int Vs, int N, int K,
-                                                         double *__restrict__ part) {
-    const int entry = blockIdx.x * kThreads + threadIdx.x;  // c * (K + 1) + k, k == K is the bias
-    const int c = entry / (K + 1), k = entry % (K + 1);
+__global__ __launch_bounds__(256) void k_bwd_wgrad_tiled(const T *__restrict__ gz, int ZS,
+                                                         const double *__restrict__ hin, int hstride, int relu, int Vs,
+                                                         int N, int K, int tiles_k, double *__restrict__ part) {
+    __shared__ T gs[kWgRows][kWgTile + 1];
+    __shared__ T hs[kWgRows][kWgTile + 1];
+    const int t = threadIdx.x, tc = t & 15, tk = t >> 4;
+    const int c0 = (blockIdx.x / tiles_k) * kWgTile, k0 = (blockIdx.x % tiles_k) * kWgTile;
     const int chunk = (Vs + gridDim.y - 1) / gridDim.y;
     const int v0 = blockIdx.y * chunk, v1 = min(Vs, v0 + chunk);
-    if (c >= N) return;
-    T acc = 0;
-    for (int v = v0; v < v1; ++v) {
-        const T g = gz[(size_t)v * ZS + c];
-        if (k == K) {
-            acc += g;
-        } else {
-            double h = hin[(size_t)v * hstride + k];
-            if (relu) h = h > 0.0 ? h : 0.0;
-            acc += g * (T)h;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int vb = v0; vb < v1; vb += kWgRows) {
+        const int nv = min(kWgRows, v1 - vb);
+        for (int idx = t; idx < kWgRows * kWgTile; idx += 256) {
+            const int r = idx / kWgTile, q = idx % kWgTile;
+            const int v = vb + r, c = c0 + q, k = k0 + q;
+            T g = 0, h = 0;
+            if (r < nv) {
+                if (c < N) g = gz[(size_t)v * ZS + c];
+                if (k < K) {
+                    double x = hin[(size_t)v * hstride + k];
+                    if (relu) x = x > 0.0 ? x : 0.0;
+                    h = (T)x;
+                } else if (k == K) {
+                    h = 1;
+                }
+            }
+            gs[r][q] = g;
+            hs[r][q] = h;
+        }
+        __syncthreads();
+        for (int r = 0; r < nv; ++r) {
+            T a[4], bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = gs[r][tc + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bb[j] = hs[r][tk + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(a[i], bb[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = c0 + tc + 16 * i;
+        if (c >= N) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + tk + 16 * j;
+            if (k <= K) part[(size_t)blockIdx.y * N * (K + 1) + (size_t)c * (K + 1) + k] = (double)acc[i][j];
         }
     }
-    part[(size_t)blockIdx.y * N * (K + 1) + entry] = (double)acc;
 }
 
 __global__ __launch_bounds__(kThreads) void k_bwd_wreduce(const double *__restrict__ part, int chunks, int N, int K,
@@ -169,19 +213,54 @@ __global__ __launch_bounds__(kThreads) void k_bwd_wreduce(const double *__restri
 }
 
 // gz_prev[v][k] = (sum_c W[c][k] gz[v][c]) * [Z_prev[v][k] > 0] for the
-// vertices present at the layer start.
+// vertices present at the layer start. A workgroup takes 64 vertices x 64
+// columns k, stages 32 neurons c of gz and W at a time through LDS, and each
+// thread accumulates 4 x 4 entries, summing over c in order.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_prev(const T *__restrict__ gz, int ZS, const double *__restrict__ W,
-                                                        const double *__restrict__ Zprev, int ZSp, int Vs, int N, int K,
-                                                        T *__restrict__ gzp) {
-    for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < (size_t)Vs * K;
-         i += (size_t)gridDim.x * kThreads) {
-        const size_t v = i / K;
-        const int k = (int)(i % K);
-        T acc = 0;
-        if (Zprev[v * ZSp + k] > 0.0)
-            for (int c = 0; c < N; ++c) acc += (T)W[(size_t)c * K + k] * gz[v * ZS + c];
-        gzp[v * ZSp + k] = acc;
+__global__ __launch_bounds__(256) void k_bwd_prev(const T *__restrict__ gz, int ZS, const double *__restrict__ W,
+                                                  const double *__restrict__ Zprev, int ZSp, int Vs, int N, int K,
+                                                  T *__restrict__ gzp) {
+    __shared__ T gs[kWgTile][kWgRows + 1];
+    __shared__ T ws[kWgRows][kWgTile + 1];
+    const int t = threadIdx.x, tv = t & 15, tk = t >> 4;
+    const int v0 = blockIdx.x * kWgTile, k0 = blockIdx.y * kWgTile;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int cb = 0; cb < N; cb += kWgRows) {
+        const int nc = min(kWgRows, N - cb);
+        for (int idx = t; idx < kWgTile * kWgRows; idx += 256) {
+            const int r = idx / kWgRows, q = idx % kWgRows;  // gz: vertex r, neuron q
+            const int v = v0 + r;
+            gs[r][q] = (v < Vs && q < nc) ? gz[(size_t)v * ZS + cb + q] : (T)0;
+            const int cr = idx / kWgTile, kq = idx % kWgTile;  // W: neuron cr, column kq
+            ws[cr][kq] = (cr < nc && k0 + kq < K) ? (T)W[(size_t)(cb + cr) * K + k0 + kq] : (T)0;
+        }
+        __syncthreads();
+        for (int c = 0; c < nc; ++c) {
+            T a[4], bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = gs[tv + 16 * i][c];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bb[j] = ws[c][tk + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(bb[j], a[i], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int v = v0 + tv + 16 * i;
+        if (v >= Vs) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + tk + 16 * j;
+            if (k < K) gzp[(size_t)v * ZSp + k] = Zprev[(size_t)v * ZSp + k] > 0.0 ? acc[i][j] : (T)0;
+        }
     }
 }
 
@@ -220,13 +299,13 @@ void bwd_layer(const T *gz, int ZS, const double *hin, int hstride, int relu, in
                double *part, int chunks, double *gW, double *gb, T *gzp, int ZSp, hipStream_t st) {
     const int entries = N * (K + 1);
     const int gx = (entries + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_bwd_wgrad<T>, dim3(gx, chunks), dim3(kThreads), 0, st, gz, ZS, hin, hstride, relu, Vs, N, K,
-                       part);
+    const int tiles_c = (N + kWgTile - 1) / kWgTile, tiles_k = (K + 1 + kWgTile - 1) / kWgTile;
+    hipLaunchKernelGGL(k_bwd_wgrad_tiled<T>, dim3(tiles_c * tiles_k, chunks), dim3(256), 0, st, gz, ZS, hin, hstride,
+                       relu, Vs, N, K, tiles_k, part);
     hipLaunchKernelGGL(k_bwd_wreduce, dim3(gx), dim3(kThreads), 0, st, part, chunks, N, K, gW, gb);
-    if (gzp) {
-        int grid = (int)std::min<size_t>(8192, ((size_t)Vs * K + kThreads - 1) / kThreads);
-        grid = grid < 1 ? 1 : grid;
-        hipLaunchKernelGGL(k_bwd_prev<T>, dim3(grid), dim3(kThreads), 0, st, gz, ZS, W, hin, hstride, Vs, N, K, gzp);
+    if (gzp && Vs > 0) {
+        const dim3 grid((Vs + kWgTile - 1) / kWgTile, (K + kWgTile - 1) / kWgTile);
+        hipLaunchKernelGGL(k_bwd_prev<T>, grid, dim3(256), 0, st, gz, ZS, W, hin, hstride, Vs, N, K, gzp);
     }
 }
 
