@@ -497,7 +497,7 @@ struct Domain {
 // Small networks (predicted complex of at most kTinyVertices vertices) go to
 // the batched kernel as a batch of one: one launch instead of several per
 // neuron step, the same complex (PCX_NO_TINY=1 in the environment turns it off).
-constexpr double kTinyVertices = 1024.0;
+constexpr double kTinyVertices = 2500.0;
 bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
     const char *off = getenv("PCX_NO_TINY");
     if (off && off[0] == '1') return false;
@@ -509,7 +509,9 @@ bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
         N += mlp->widths[l];
         Wd += (mlp->widths[l] + 31) / 32;
     }
-    return Wd <= kBatchMaxWords && N > 0 && predict_vertices(mlp->D, N) <= kTinyVertices;
+    double limit = kTinyVertices;
+    if (const char *v = getenv("PCX_TINY_VERTICES")) limit = atof(v);
+    return Wd <= kBatchMaxWords && N > 0 && predict_vertices(mlp->D, N) <= limit;
 }
 
 int extract_impl(const pcx_mlp *mlp, const Domain &dom, const pcx_opts *opts, pcx_complex **out,
