@@ -260,7 +260,7 @@ typedef struct pcx_server pcx_server;
 typedef struct {
     uint64_t mem_budget;    /* bytes of predicted device memory in flight; 0 = 64 GiB */
     int32_t max_batch;      /* jobs per tick; 0 = 4096 */
-    int32_t large_workers;  /* concurrent per-step extractions; 0 = 3 */
+    int32_t large_workers;  /* concurrent per-step extractions; 0 = 6 */
     int32_t include_output; /* as pcx_opts.include_output, for every request */
     int32_t small_vertices; /* batched-kernel threshold on the predicted vertex count; 0 = 65536 */
 } pcx_server_opts;

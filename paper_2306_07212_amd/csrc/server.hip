@@ -238,7 +238,7 @@ int pcx_server_create(const pcx_server_opts *opts, pcx_server **out) {
     if (opts) s->opts = *opts;
     if (s->opts.mem_budget == 0) s->opts.mem_budget = 64ull << 30;
     if (s->opts.max_batch <= 0) s->opts.max_batch = 4096;
-    if (s->opts.large_workers <= 0) s->opts.large_workers = 3;
+    if (s->opts.large_workers <= 0) s->opts.large_workers = 6;
     if (s->opts.small_vertices <= 0) s->opts.small_vertices = 65536;
     (void)hipGetDevice(&s->device);
     if (hipStreamCreateWithFlags(&s->tick_stream, hipStreamNonBlocking) != hipSuccess) {
