@@ -114,7 +114,7 @@ def _predicted_vertices(D, N):
 
 def test_served_workload_prefix_identical_alone_and_oracle(pcx, oracle_lib):
     """The first 64 requests of the served workload (D in {2,3}, widths 16-128,
-    depths 2-4, the bench's seeds) arrive in bursts of eight, so many run
+    depths 2-4, the bench's seeds) arrive in bursts of sixteen, so many run
     together: batched ticks and per-step workers overlap on the device. Every
     result is bit-identical to the same request extracted alone, and every
     request whose complex is small enough for the oracle (about 100K vertices)
@@ -132,7 +132,7 @@ def test_served_workload_prefix_identical_alone_and_oracle(pcx, oracle_lib):
     tickets = []
     for k, (r, m) in enumerate(zip(reqs, mlps)):
         # each burst at the arrival time of its first request
-        dt = reqs[k - k % 8].arrival_s - (time.perf_counter() - t0)
+        dt = reqs[k - k % 16].arrival_s - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(m, r.box.lo, r.box.hi))
