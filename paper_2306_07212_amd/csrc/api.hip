@@ -439,25 +439,23 @@ int pcx_mlp_create(int32_t n_layers, const int32_t *widths, const double *const 
         tmp.resize((size_t)nin * nout);
         for (int i = 0; i < nout; ++i)
             for (int k = 0; k < nin; ++k) tmp[(size_t)k * nout + i] = W[l][(size_t)i * nin + k];
-        double *dw = nullptr, *db = nullptr;
-        std::shared_lock<std::shared_mutex> gate(capture_gate());
-        if (hipMalloc((void **)&dw, tmp.size() * sizeof(double)) != hipSuccess ||
-            hipMalloc((void **)&db, (size_t)nout * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            if (dw) (void)hipFree(dw);
+        double *dw = nullptr, *db = nullptr, *dr = nullptr;
+        bool ok;
+        {
+            std::shared_lock<std::shared_mutex> gate(capture_gate());
+            ok = hipMalloc((void **)&dw, tmp.size() * sizeof(double)) == hipSuccess &&
+                 hipMalloc((void **)&db, (size_t)nout * sizeof(double)) == hipSuccess &&
+                 hipMalloc((void **)&dr, tmp.size() * sizeof(double)) == hipSuccess;
+            if (!ok) (void)hipGetLastError();
+        }
+        // (pcx_mlp_free takes the gate itself: it is not held here)
+        if (dw) m->Wt.push_back(dw);
+        if (db) m->b.push_back(db);
+        if (dr) m->Wr.push_back(dr);
+        if (!ok) {
             pcx_mlp_free(m);
             return fail(PCX_ERR_OOM, "hipMalloc for weights failed");
         }
-        m->Wt.push_back(dw);
-        m->b.push_back(db);
-        double *dr = nullptr;
-        if (hipMalloc((void **)&dr, tmp.size() * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            pcx_mlp_free(m);
-            return fail(PCX_ERR_OOM, "hipMalloc for weights failed");
-        }
-        m->Wr.push_back(dr);
-        gate.unlock();
         if (copy_sync(dw, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice) ||
             copy_sync(dr, W[l], tmp.size() * sizeof(double), hipMemcpyHostToDevice) ||
             copy_sync(db, b[l], (size_t)nout * sizeof(double), hipMemcpyHostToDevice)) {
