@@ -223,7 +223,8 @@ int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, c
 /* Per-network info / copy; PCX_ERR_DEGENERATE for a non-generic network. */
 int pcx_batch_info(const pcx_batch *bt, int32_t i, pcx_info *info);
 int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *signs, int32_t *edges);
-/* Per-step counters of network i (as pcx_complex_steps: n_steps rows of 4 int64, host). */
+/* Per-step counters of network i (as pcx_complex_steps: n_steps rows of 4 int64, host);
+ * they stay on the device until asked for. */
 int pcx_batch_steps(const pcx_batch *bt, int32_t i, int64_t *steps);
 int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *stats);
 void pcx_batch_free(pcx_batch *bt);

@@ -23,7 +23,9 @@ struct pcx_batch {
     int workgroups = 0, wg_per_cu = 0, n_fallback = 0;
     int sched = 0;                            // schedule bits of the launch (kSched*)
     std::vector<int> sig;                     // size signature of the batched networks
-    std::vector<std::vector<int64_t>> steps;  // per-step counters of each batched network (when kept)
+    std::vector<std::vector<int64_t>> steps;  // per-step counters of each batched network (kStepsNow)
+    StepRec *rec_dev = nullptr;               // the same, still on the device (kStepsLater)
+    std::vector<size_t> rec_off;              //   network i's first record
     std::vector<int> nsub, ZS;
     std::vector<std::vector<uint64_t>> valid;
 };
@@ -46,10 +48,14 @@ std::vector<int> signature(const std::vector<int> &nsteps, const std::vector<int
 
 namespace {
 
-// The batched extraction; with keep_steps, every batched network's per-step
-// counters are logged too (the batch of one behind small pcx_extract calls).
+// The batched extraction. steps: kStepsNow copies every batched network's
+// per-step counters to the host at once (the batch of one behind small
+// pcx_extract calls); kStepsLater keeps them on the device for
+// pcx_batch_steps to copy one network's on request; kStepsNone logs nothing.
+enum { kStepsNone = 0, kStepsNow = 1, kStepsLater = 2 };
 int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi, const pcx_opts *opts,
-              bool keep_steps, pcx_batch **out, int force_sched = -1) {
+              int steps_mode, pcx_batch **out, int force_sched = -1) {
+    const bool keep_steps = steps_mode != kStepsNone;
     if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (n < 0 || (n > 0 && (!mlps || !lo || !hi))) return fail(PCX_ERR_INVALID, "NULL argument");
@@ -104,7 +110,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
         bt->nsteps[i] = N;
         bt->nsub[i] = nsub;
         bt->ZS[i] = ZS;
-        if (keep_steps) {
+        if (steps_mode == kStepsNow) {
             std::vector<uint64_t> v(Wd, 0);
             for (int e = 0; e < 2 * D; ++e) v[0] |= 1ull << (2 * e);
             int w0 = 1;
@@ -223,8 +229,19 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
         if (keep_steps) {
             size_t tot = 0;
             for (int i : batched) tot += (size_t)bt->nsteps[i];
-            if ((rc = ar.alloc(&p, std::max<size_t>(tot, 1) * sizeof(StepRec)))) goto fail_out;
-            rec_dev = (StepRec *)p;
+            if (steps_mode == kStepsLater) {
+                // kept by the batch (returned to the pool by pcx_batch_free)
+                size_t got = 0;
+                rec_dev = (StepRec *)pool().get(std::max<size_t>(tot, 1) * sizeof(StepRec), &got, ~(size_t)0);
+                if (!rec_dev) {
+                    rc = fail(PCX_ERR_OOM, "step log of the batch");
+                    goto fail_out;
+                }
+                bt->rec_dev = rec_dev;
+            } else {
+                if ((rc = ar.alloc(&p, std::max<size_t>(tot, 1) * sizeof(StepRec)))) goto fail_out;
+                rec_dev = (StepRec *)p;
+            }
             size_t off = 0;
             for (int i : batched) {
                 nets[i].rec = rec_dev + off;
@@ -232,6 +249,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
                 off += (size_t)bt->nsteps[i];
             }
             rec_tot = tot;
+            if (steps_mode == kStepsLater) bt->rec_off = rec_off;
         }
         A.n = (int)batched.size();
         A.arena_bytes = abytes;
@@ -264,11 +282,12 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
             HIPCHK(hipGetLastError());
             HIPCHK(hipEventRecord(e1, st));
             HIPCHK(hipMemcpyAsync(bt->res.data(), A.res, (size_t)n * sizeof(BatchResult), hipMemcpyDeviceToHost, st));
-            std::vector<StepRec> rec(rec_tot);
-            if (rec_tot) HIPCHK(hipMemcpyAsync(rec.data(), rec_dev, rec_tot * sizeof(StepRec), hipMemcpyDeviceToHost, st));
+            std::vector<StepRec> rec(steps_mode == kStepsNow ? rec_tot : 0);
+            if (!rec.empty())
+                HIPCHK(hipMemcpyAsync(rec.data(), rec_dev, rec_tot * sizeof(StepRec), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             for (int i : batched) {
-                if (!keep_steps || bt->res[i].status != BATCH_OK) continue;
+                if (steps_mode != kStepsNow || bt->res[i].status != BATCH_OK) continue;
                 auto &sv = bt->steps[i];
                 sv.resize((size_t)bt->nsteps[i] * 4);
                 for (int k = 0; k < bt->nsteps[i]; ++k) {
@@ -339,7 +358,7 @@ fail_out:
 
 extern "C" int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
                                  const pcx_opts *opts, pcx_batch **out) {
-    return batch_run(n, mlps, lo, hi, opts, true, out);
+    return batch_run(n, mlps, lo, hi, opts, kStepsLater, out);
 }
 
 namespace pcx {
@@ -352,7 +371,7 @@ int tiny_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const p
     *out = nullptr;
     pcx_batch *bt = nullptr;
     const pcx_mlp *const one[1] = {mlp};
-    int rc = batch_run(1, one, lo, hi, &o, true, &bt);
+    int rc = batch_run(1, one, lo, hi, &o, kStepsNow, &bt);
     if (rc) return rc;
     const BatchResult &r = bt->res[0];
     if (r.status == BATCH_DEGENERATE) {
@@ -434,7 +453,23 @@ int pcx_batch_steps(const pcx_batch *bt, int32_t i, int64_t *steps) {
     const BatchResult &r = bt->res[i];
     if (r.status == BATCH_DEGENERATE) return fail(PCX_ERR_DEGENERATE, "network is not generic");
     if (bt->fallback[i]) return pcx_complex_steps(bt->fallback[i], steps);
-    std::memcpy(steps, bt->steps[i].data(), bt->steps[i].size() * sizeof(int64_t));
+    if (!bt->steps[i].empty()) {
+        std::memcpy(steps, bt->steps[i].data(), bt->steps[i].size() * sizeof(int64_t));
+        return PCX_OK;
+    }
+    if (!bt->rec_dev) return fail(PCX_ERR_INVALID, "the batch kept no step log");
+    // this network's records, from the device
+    const int ns = bt->nsteps[i];
+    std::vector<StepRec> rec(ns);
+    int rc;
+    if ((rc = copy_sync(rec.data(), bt->rec_dev + bt->rec_off[i], (size_t)ns * sizeof(StepRec), hipMemcpyDeviceToHost)))
+        return rc;
+    for (int k = 0; k < ns; ++k) {
+        steps[(size_t)k * 4 + 0] = rec[k].V0;
+        steps[(size_t)k * 4 + 1] = rec[k].E0;
+        steps[(size_t)k * 4 + 2] = rec[k].S;
+        steps[(size_t)k * 4 + 3] = 2 * ((int64_t)rec[k].E1 - rec[k].E0 - rec[k].S);
+    }
     return PCX_OK;
 }
 
@@ -467,6 +502,7 @@ void pcx_batch_free(pcx_batch *bt) {
     pool().put(bt->oX);
     pool().put(bt->oSG);
     pool().put(bt->oE);
+    pool().put(bt->rec_dev);
     for (auto *c : bt->fallback) pcx_complex_free(c);
     delete bt;
 }
@@ -483,7 +519,7 @@ int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, cons
             if (opts) o = *opts;
             o.batch_wg_per_cu = wpc;
             pcx_batch *bt = nullptr;
-            int rc = batch_run(n, mlps, lo, hi, &o, false, &bt, sched);
+            int rc = batch_run(n, mlps, lo, hi, &o, kStepsNone, &bt, sched);
             if (rc) return rc;
             *ms = std::min(*ms, bt->kernel_ms);
             sig = bt->sig;
