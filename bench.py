@@ -701,7 +701,9 @@ def main():
         cx.close()
         print(f"[bench] warmup {i}: V={info.V} E={info.E} splits={info.total_splits} "
               f"{1e3 * (time.perf_counter() - t):.1f} ms  kernels(ms): "
-              + " ".join(f"{f}={fam_ms[f]:.1f}" for f in FAMILIES), file=sys.stderr, flush=True)
+              + " ".join(f"{f}={fam_ms[f]:.1f}" for f in FAMILIES)
+              + ("  (every launch timed; this first run also creates the HIP events later runs reuse)"
+                 if i == 0 else ""), file=sys.stderr, flush=True)
     dom = max(FAMILIES, key=lambda f: fam_ms[f])
 
     # timed region: K extractions; in the last one every launch of the dominant
