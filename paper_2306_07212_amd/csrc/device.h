@@ -141,10 +141,14 @@ __device__ __forceinline__ uint32_t match16(const uint16_t *__restrict__ nxt, in
 // slot from it and records the pair at once: each of the two slots gets a
 // record naming the other, tagged with the step. The pairing then checks that
 // every valid slot's record is fresh and mutual. A face met once leaves its
-// slot without a fresh record; a face reached a third time leaves a record the
-// partner does not return (a slot names one partner only); two faces that share
-// 39 key bits and a probe chain are paired and then fail the word-by-word
-// comparison. Each of these sends the step to the exact pass.
+// slot without a fresh record; a word reached three or more times leaves a
+// record its partner does not return (a slot names one partner only) -- and
+// two different faces whose keys are equal (the hash bits beside the slot
+// field, at most 39) and whose probe chains meet put four arrivals on one
+// word, so for a generic input no wrong pair gets through. Each of these sends
+// the step to the exact pass. With verify_pairs the emission also compares the
+// two perturbed sign rows, which catches two faces each met once (a non-generic
+// input) with equal keys.
 
 // pairing failures: recorded with their step (the exact pass redoes that step)
 __device__ __forceinline__ void raise_pair_flag(int *ctr, int f, int step) {
