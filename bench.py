@@ -133,9 +133,15 @@ KERNEL_FAMILY = {"pcx::k_gemm": "gemm", "pcx::k_next_all": "next", "pcx::k_sel_"
 
 
 def kernels_sha256():
+    """Digest of the kernel sources' code (comments and blank space dropped, so
+    that an edited comment keeps counters taken on the same code valid)."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2306_07212_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_2306_07212_amd", "csrc", f)).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 
