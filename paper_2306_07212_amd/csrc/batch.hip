@@ -229,9 +229,13 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                 if (t == 0 && net.rec) net.rec[step] = StepRec{V, E, 0, E};
                 continue;
             }
-            uint32_t tsz = 256;
+            if (V + S > Vcap || E + S * D > Ecap || S * P > Kcap) {
+                status = BATCH_OVERFLOW;
+                break;
+            }
+            uint32_t tsz = 256;  // (S * P <= Kcap: the doubling ends)
             while (tsz < 2u * (uint32_t)(S * P)) tsz <<= 1;
-            if (V + S > Vcap || E + S * D > Ecap || S * P > Kcap || tsz > A.tcap) {
+            if (tsz > A.tcap) {
                 status = BATCH_OVERFLOW;
                 break;
             }

@@ -170,7 +170,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
         int ecap = (int)(((size_t)vcap * (maxD + 1) + 15) / 16 * 16);
         int kcap = (int)std::max<size_t>(1024, (size_t)P * std::max<size_t>(256, vcap / 12));
         uint32_t tcap = 256;
-        while (tcap < 2u * (uint32_t)kcap) tcap <<= 1;
+        while ((uint64_t)tcap < 2ull * (uint64_t)kcap && tcap < (1u << 31)) tcap <<= 1;
         size_t abytes = batch_arena_bytes(vbytes, ecap, kcap, tcap);
         abytes = (abytes + 255) / 256 * 256;
         // workgroups per CU and schedule: from the autotuner's cache, else 2 and the default

@@ -63,8 +63,8 @@ struct Carve {
     }
 };
 
-uint32_t pow2_at_least(size_t n) {
-    uint32_t t = 256;
+size_t pow2_at_least(size_t n) {
+    size_t t = 256;
     while (t < n) t <<= 1;
     return t;
 }
@@ -108,7 +108,7 @@ extern "C" int pcx_extract_into(const pcx_mlp *mlp, const double *lo, const doub
     const size_t Vcap = (size_t)max_vertices, Ecap = (size_t)max_edges;
     // a step splits at most min(Vcap, Ecap) edges: that many splits' key slots
     const size_t Scap = std::min(Vcap, Ecap), Kcap = std::max<size_t>(1, (size_t)P * Scap);
-    const uint32_t Tcap = pow2_at_least(2 * Kcap);
+    const size_t Tcap = pow2_at_least(2 * Kcap);  // (huge maxima fail the scratch check below)
 
     // the scratch layout for these maxima (first with a null base, to size it)
     Bufs b{};

@@ -70,7 +70,18 @@ def test_capacity_errors_are_reported(pcx):
     with pytest.raises(pcx.PcxError) as e:
         into(pcx, wl.plain_large(), False, max_v=1 << 22, max_e=1 << 23)
     assert e.value.code == pcx.PCX_ERR_CAPACITY and "scratch" in str(e.value)
-    # and the entry point still works after both
+    # maxima near 2^31 (key slots beyond 32 bits) are refused the same way, before any buffer is touched
+    import torch
+    dev = torch.device("cuda:0")
+    tiny = [torch.zeros(8, dtype=t, device=dev) for t in (torch.float64, torch.int64, torch.int32)]
+    m = pcx.MLP.from_net(wl.plain_large())
+    box = wl.cube(3)
+    with pytest.raises(pcx.PcxError) as e:
+        pcx.extract_into(m, box.lo, box.hi, tiny[0].data_ptr(), tiny[1].data_ptr(), tiny[2].data_ptr(),
+                         (1 << 31) - 2, (1 << 31) - 2)
+    assert e.value.code == pcx.PCX_ERR_CAPACITY and "scratch" in str(e.value)
+    m.close()
+    # and the entry point still works after all of them
     got, _, info = into(pcx, net, False, max_v=4 * rinfo.V, max_e=4 * rinfo.E)
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
