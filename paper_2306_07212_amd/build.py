@@ -34,6 +34,12 @@ def flags():
     ]
 
 
+# per-source additions: the batched kernel's MFMAs accumulate in ordinary
+# VGPRs (accumulation registers would add to the split's register count and
+# halve the kernel's occupancy)
+EXTRA = {"batch.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def build(verbose: bool = False) -> str:
     objs = []
     cc = hipcc()
@@ -41,7 +47,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *flags(), *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

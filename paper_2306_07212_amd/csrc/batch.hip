@@ -113,6 +113,99 @@ __device__ int block_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int 
     return run;
 }
 
+// Step 1 (Sec. 4.2) for one layer of at most 64 neurons, by the whole
+// workgroup on the matrix cores: each wave takes strips of 16 vertex rows and
+// computes all 16 CT >= N columns of a strip with FP64 16x16x4 MFMAs (A lane l:
+// row l%16, k l/16; B lane l: k l/16, column l%16; result lane l, value i:
+// row l/16 + 4i, column l%16), its inputs and the weights read straight from
+// memory (no LDS, no barrier: a wave reads every input of its rows before it
+// writes them, so the evaluation can be in place). A chain of these MFMAs
+// rounds as the sequential FMA chain over k from zero does (the zero padding
+// of k adds +0 to a sum that is never -0), and then + bias: the values are
+// those of every other evaluation kernel, bit for bit.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// (Not inlined, and given plain pointers rather than the workgroup's Bufs, so
+// that its registers and the Bufs stay out of the split's register allocation.)
+template <int CT>
+__device__ __noinline__ void eval_mfma(double *Zo, uint64_t *SGo, uint64_t *LWo, int *ctr, int ZS, const double *in,
+                                       int in_stride, int relu, int V, int K, int N, const double *__restrict__ Wt,
+                                       const double *__restrict__ bias, int Wd, int lw0) {
+    const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = l & 15, q = l >> 4;
+    double bv[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) bv[ct] = ct * 16 + r < N ? bias[ct * 16 + r] : 0.0;
+    int zero = 0;
+    for (int v0 = wave * 16; v0 < V; v0 += 16 * (kThreads / 64)) {
+        const bool arow = v0 + r < V;
+        const double *hp = in + (size_t)(arow ? v0 + r : 0) * in_stride;
+        dbl4 acc[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+        // one k-step of 4 per MFMA; the next step's operands are loaded before
+        // this step's MFMAs issue
+        double af, bf[CT];
+        auto load = [&](int k0, double &a, double *bw) {
+            const int k = k0 + q;
+            const double h = (arow && k < K) ? hp[k] : 0.0;
+            a = relu ? (h > 0.0 ? h : 0.0) : h;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int col = ct * 16 + r;
+                bw[ct] = (k < K && col < N) ? Wt[(size_t)k * N + col] : 0.0;
+            }
+        };
+        load(0, af, bf);
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            double an = 0.0, bn[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) bn[ct] = 0.0;
+            if (k0 + 4 < K) load(k0 + 4, an, bn);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[ct], acc[ct], 0, 0, 0);
+            af = an;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) bf[ct] = bn[ct];
+        }
+        // bias, store, and the layer's sign words (word p from tiles 2p and 2p+1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = v0 + q + 4 * i;
+            uint64_t pb[CT], nb[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int col = ct * 16 + r;
+                const bool ok = v < V && col < N;
+                double z = 0.0;
+                if (ok) {
+                    z = acc[ct][i] + bv[ct];
+                    Zo[(size_t)v * ZS + col] = z;
+                    zero |= (z == 0.0);
+                }
+                pb[ct] = __ballot(ok && z > 0.0);
+                nb[ct] = __ballot(ok && z < 0.0);
+            }
+            const int sh = 16 * q;
+#pragma unroll
+            for (int p = 0; p < (CT + 1) / 2; ++p) {
+                if (r == p && v < V) {
+                    uint32_t pos = (uint32_t)((pb[2 * p] >> sh) & 0xFFFFu);
+                    uint32_t neg = (uint32_t)((nb[2 * p] >> sh) & 0xFFFFu);
+                    if (2 * p + 1 < CT) {
+                        pos |= (uint32_t)((pb[2 * p + 1] >> sh) & 0xFFFFu) << 16;
+                        neg |= (uint32_t)((nb[2 * p + 1] >> sh) & 0xFFFFu) << 16;
+                    }
+                    const uint64_t cw = codes_of(pos, neg);
+                    SGo[(size_t)v * Wd + lw0 + p] = cw;
+                    if (LWo) LWo[(size_t)v * 8 + p] = cw;
+                }
+            }
+        }
+    }
+    if (zero) raise_flag(ctr, FLAG_ZERO_SIGN);
+}
+
 template <int G, int NC>
 __device__ __forceinline__ void block_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S) {
     constexpr int groups = kThreads / G;
@@ -204,10 +297,19 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
     int step = 0;  // neuron steps of this network so far (tags its partner records)
     for (int l = 0; l < nsub && status == BATCH_OK; ++l) {
         const int N = net.widths[l + 1], K = net.widths[l];
-        // step 1 for the layer, in place, one 32-row tile at a time
-        for (int v0 = 0; v0 < V; v0 += kGemmRows)
-            gemm_tile(b, ZS, l == 0 ? b.X : b.Z, l == 0 ? D : ZS, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l], v0,
-                      gl->hs, gl->ws);
+        // step 1 for the layer, in place: layers of up to 64 neurons on the
+        // matrix cores, wider ones one 32-row tile at a time
+        {
+            const double *in = l == 0 ? b.X : b.Z;
+            const int ins = l == 0 ? D : ZS;
+            if (N <= 16) eval_mfma<1>(b.Z, b.SG, b.LW, b.CTR, ZS, in, ins, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l]);
+            else if (N <= 32) eval_mfma<2>(b.Z, b.SG, b.LW, b.CTR, ZS, in, ins, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l]);
+            else if (N <= 48) eval_mfma<3>(b.Z, b.SG, b.LW, b.CTR, ZS, in, ins, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l]);
+            else if (N <= 64) eval_mfma<4>(b.Z, b.SG, b.LW, b.CTR, ZS, in, ins, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l]);
+            else
+                for (int v0 = 0; v0 < V; v0 += kGemmRows)
+                    gemm_tile(b, ZS, in, ins, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l], v0, gl->hs, gl->ws);
+        }
         __syncthreads();
         for (int e = t; e < E; e += kThreads) {
             const int2 ab = b.EDG[e];
