@@ -269,7 +269,7 @@ def form_batched(args, pcx, wl, torch):
             "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": b8, "kernel": "pcx::k_batch",
             "launches_per_step": 1, "avg_launch_us": k_med * 1e6, "traffic": None,
             "bytes_rule": "scope-table count summed over every network's steps; the launch also evaluates "
-                          "every layer (FP64 FMA, not in the count)"}
+                          "every layer (FP64 MFMA for layers of up to 64 neurons, not in the count)"}
     # per-step path (ordinary per-step kernels, each network once) on a stratified sample
     os.environ["PCX_NO_TINY"] = "1"
     os.environ["PCX_NO_GRAPH"] = "1"

@@ -124,9 +124,10 @@ void pcx_mlp_free(pcx_mlp *mlp);
  * steps differ from the log is discarded and the ordinary path runs. A capture
  * waits for no other call: while another thread of the process is inside a
  * device allocation or free of this library it is skipped until a later
- * request. A network whose predicted complex has at most 2500 vertices runs as
- * a batch of one instead (one launch of the batched kernel, the same complex;
- * PCX_NO_TINY=1 turns this off, PCX_TINY_VERTICES sets the threshold). */
+ * request. A network whose predicted complex is small (at most 7500 vertices
+ * for D <= 2, 1500 for D = 3; never for D >= 4) runs as a batch of one instead
+ * (one launch of the batched kernel, the same complex; PCX_NO_TINY=1 turns
+ * this off, PCX_TINY_VERTICES sets the threshold for every D). */
 int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts,
                 pcx_complex **out);
 

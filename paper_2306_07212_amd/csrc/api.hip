@@ -492,10 +492,13 @@ struct Domain {
     std::vector<int2> E0;                       // [ne]
 };
 
-// Small networks (predicted complex of at most kTinyVertices vertices) go to
-// the batched kernel as a batch of one: one launch instead of several per
-// neuron step, the same complex (PCX_NO_TINY=1 in the environment turns it off).
-constexpr double kTinyVertices = 2500.0;
+// Small networks go to the batched kernel as a batch of one: one launch
+// instead of several per neuron step, the same complex (PCX_NO_TINY=1 in the
+// environment turns it off). Up to which predicted vertex count, by input
+// dimension: where one workgroup stops being faster than the per-step kernels
+// (measured crossovers near 4,200 actual vertices for D = 2 and 1,200 for
+// D = 3; for D >= 4 the per-step kernels were faster at every size tried).
+double tiny_vertices(int D) { return D <= 2 ? 7500.0 : D == 3 ? 1500.0 : 0.0; }
 bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
     const char *off = getenv("PCX_NO_TINY");
     if (off && off[0] == '1') return false;
@@ -507,7 +510,7 @@ bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
         N += mlp->widths[l];
         Wd += (mlp->widths[l] + 31) / 32;
     }
-    double limit = kTinyVertices;
+    double limit = tiny_vertices(mlp->D);
     if (const char *v = getenv("PCX_TINY_VERTICES")) limit = atof(v);
     return Wd <= kBatchMaxWords && N > 0 && predict_vertices(mlp->D, N) <= limit;
 }
