@@ -124,8 +124,8 @@ void pcx_mlp_free(pcx_mlp *mlp);
  * steps differ from the log is discarded and the ordinary path runs. A capture
  * waits for no other call: while another thread of the process is inside a
  * device allocation or free of this library it is skipped until a later
- * request. A network whose predicted complex is small (at most 7500 vertices
- * for D <= 2, 1500 for D = 3; never for D >= 4) runs as a batch of one instead
+ * request. A network whose predicted complex is small (at most 15000 vertices
+ * for D <= 2, 3500 for D = 3; never for D >= 4) runs as a batch of one instead
  * (one launch of the batched kernel, the same complex; PCX_NO_TINY=1 turns
  * this off, PCX_TINY_VERTICES sets the threshold for every D). */
 int pcx_extract(const pcx_mlp *mlp, const double *lo, const double *hi, const pcx_opts *opts,
@@ -216,7 +216,8 @@ typedef struct {
     int32_t workgroups, wg_per_cu;
     double kernel_ms;       /* device time of the persistent launch */
     double time_ms;         /* host wall time of the whole call */
-    int32_t split_lanes;    /* schedule of the launch: lanes per splitting edge (32 or 64) */
+    int32_t split_lanes;    /* schedule of the launch: lanes per splitting edge (16, 32 or 64;
+                             * 16 applies to layers of up to 128 neurons, 32 to wider ones) */
     int32_t select_items;   /*   and edges per thread in each step's compaction (16 or 8) */
 } pcx_batch_stats;
 int pcx_extract_batch(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,
@@ -229,9 +230,9 @@ int pcx_batch_copy(const pcx_batch *bt, int32_t i, double *coords, uint64_t *sig
 int pcx_batch_steps(const pcx_batch *bt, int32_t i, int64_t *steps);
 int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *stats);
 void pcx_batch_free(pcx_batch *bt);
-/* Autotuner: times the batch's persistent launch under each schedule (lanes
- * per splitting edge 32 or 64, edges per thread in each step's compaction 16
- * or 8) at 2 workgroups per compute unit, then 1 and 4 workgroups per compute
+/* Autotuner: times the batch's persistent launch under each of six schedules
+ * (lanes per splitting edge 16, 32 or 64; edges per thread in each step's
+ * compaction 16 or 8) at 2 workgroups per compute unit, then 1 and 4 workgroups per compute
  * unit under the best schedule (best of two launches each), and keeps the
  * fastest for batches with the same size signature (the sorted subdivided-
  * neuron counts and input dimensions of the batched networks); later
@@ -240,7 +241,7 @@ void pcx_batch_free(pcx_batch *bt);
 typedef struct {
     int32_t wg_per_cu, split_lanes, select_items;
     int32_t candidates;     /* launches configurations timed */
-    double ms_default;      /* kernel time with the default schedule: 2 per CU, 32 lanes, 16 edges */
+    double ms_default;      /* kernel time with the default schedule: 2 per CU, 16 lanes, 16 edges */
     double ms_best;         /* kernel time with the chosen one */
 } pcx_batch_tuning;
 int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, const double *hi,

@@ -496,9 +496,9 @@ struct Domain {
 // instead of several per neuron step, the same complex (PCX_NO_TINY=1 in the
 // environment turns it off). Up to which predicted vertex count, by input
 // dimension: where one workgroup stops being faster than the per-step kernels
-// (measured crossovers near 4,200 actual vertices for D = 2 and 1,200 for
-// D = 3; for D >= 4 the per-step kernels were faster at every size tried).
-double tiny_vertices(int D) { return D <= 2 ? 7500.0 : D == 3 ? 1500.0 : 0.0; }
+// (measured crossovers near 10,000 actual vertices for D = 2 and 2,800 for
+// D = 3; for D >= 4 the per-step kernels were faster at nearly every size tried).
+double tiny_vertices(int D) { return D <= 2 ? 15000.0 : D == 3 ? 3500.0 : 0.0; }
 bool tiny_eligible(const pcx_mlp *mlp, const pcx_opts &o, int nsub) {
     const char *off = getenv("PCX_NO_TINY");
     if (off && off[0] == '1') return false;

@@ -26,8 +26,13 @@ struct BatchNet {
 };
 
 // schedule bits of a batched launch (0: 16 edges per thread in each step's
-// compaction, 32 lanes per splitting edge)
-enum { kSchedSelect8 = 1, kSchedSplit64 = 2, kSchedCount = 4 };
+// compaction, 32 lanes per splitting edge; kSchedSplit16: 16 lanes per
+// splitting edge in layers of up to 128 neurons). The schedules are the values
+// 0 .. kSchedCount-1 (kSchedSplit64 and kSchedSplit16 exclude each other).
+enum { kSchedSelect8 = 1, kSchedSplit64 = 2, kSchedSplit16 = 4, kSchedCount = 6 };
+// the schedule of an untuned batch: 16 edges per thread, 16 lanes per split
+constexpr int kSchedDefault = kSchedSplit16;
+inline int sched_split_lanes(int sched) { return (sched & kSchedSplit64) ? 64 : (sched & kSchedSplit16) ? 16 : 32; }
 
 struct BatchResult {
     int status, V, E, Wd;

@@ -367,7 +367,12 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                 for (uint32_t i = t; i < tsz; i += kThreads) table[i] = 0ull;
                 __syncthreads();
             }
-            if (GS == 32) {
+            if (GS == 16) {
+                if (N <= 32) block_split<16, 2>(b, g, V, E, S);
+                else if (N <= 64) block_split<16, 4>(b, g, V, E, S);
+                else if (N <= 128) block_split<16, 8>(b, g, V, E, S);
+                else block_split<32, 8>(b, g, V, E, S);
+            } else if (GS == 32) {
                 if (N <= 32) block_split<32, 1>(b, g, V, E, S);
                 else if (N <= 64) block_split<32, 2>(b, g, V, E, S);
                 else if (N <= 128) block_split<32, 4>(b, g, V, E, S);
@@ -445,7 +450,7 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
 
 // the persistent kernel for one schedule (SI, GS) of the whole batch
 template <int SI, int GS>
-__global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A) {
+__global__ __launch_bounds__(kThreads, 2) void k_batch(BatchArgs A) {
     __shared__ GemmLds gl;
     __shared__ int s_w[kThreads / 64];
     __shared__ int s_misc[8];
@@ -468,6 +473,10 @@ void launch_batch(const BatchArgs &A, int grid, int sched, hipStream_t st) {
         case kSchedSplit64: hipLaunchKernelGGL((k_batch<16, 64>), dim3(grid), dim3(kThreads), 0, st, A); break;
         case kSchedSelect8 | kSchedSplit64:
             hipLaunchKernelGGL((k_batch<8, 64>), dim3(grid), dim3(kThreads), 0, st, A);
+            break;
+        case kSchedSplit16: hipLaunchKernelGGL((k_batch<16, 16>), dim3(grid), dim3(kThreads), 0, st, A); break;
+        case kSchedSelect8 | kSchedSplit16:
+            hipLaunchKernelGGL((k_batch<8, 16>), dim3(grid), dim3(kThreads), 0, st, A);
             break;
         default: hipLaunchKernelGGL((k_batch<16, 32>), dim3(grid), dim3(kThreads), 0, st, A); break;
     }

@@ -176,7 +176,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
         // workgroups per CU and schedule: from the autotuner's cache, else 2 and the default
         const std::vector<int> sig = signature(bt->nsteps, bt->D, batched);
         bt->sig = sig;
-        int wpc = 2, sched = 0;
+        int wpc = 2, sched = kSchedDefault;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find(sig);
@@ -490,7 +490,7 @@ int pcx_batch_summary(const pcx_batch *bt, pcx_batch_stats *s) {
     s->fallbacks = bt->n_fallback;
     s->workgroups = bt->workgroups;
     s->wg_per_cu = bt->wg_per_cu;
-    s->split_lanes = (bt->sched & kSchedSplit64) ? 64 : 32;
+    s->split_lanes = sched_split_lanes(bt->sched);
     s->select_items = (bt->sched & kSchedSelect8) ? 8 : 16;
     s->kernel_ms = bt->kernel_ms;
     s->time_ms = bt->time_ms;
@@ -527,12 +527,14 @@ int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, cons
         }
         return PCX_OK;
     };
-    int rc, best_sched = 0, best_wpc = 2, tried = 0;
+    int rc, best_sched = kSchedDefault, best_wpc = 2, tried = 0;
     double ms_default = 0, best = 1e300, ms;
-    for (int sc = 0; sc < kSchedCount; ++sc) {
+    for (int i = 0; i < kSchedCount; ++i) {
+        // the default first, then the others in order
+        const int sc = i == 0 ? kSchedDefault : (i <= kSchedDefault ? i - 1 : i);
         if ((rc = measure(2, sc, &ms))) return rc;
         ++tried;
-        if (sc == 0) ms_default = ms;
+        if (i == 0) ms_default = ms;
         if (ms < best) {
             best = ms;
             best_sched = sc;
@@ -552,7 +554,7 @@ int pcx_batch_tune(int32_t n, const pcx_mlp *const *mlps, const double *lo, cons
     }
     if (result) {
         result->wg_per_cu = best_wpc;
-        result->split_lanes = (best_sched & kSchedSplit64) ? 64 : 32;
+        result->split_lanes = sched_split_lanes(best_sched);
         result->select_items = (best_sched & kSchedSelect8) ? 8 : 16;
         result->candidates = tried;
         result->ms_default = ms_default;

@@ -337,8 +337,8 @@ struct GemmLds {
 };
 
 // -------------------------------------------- steps 4-5a: split and keys
-// The work of one splitting edge s for a group of G lanes (lane = 0..G-1;
-// half = which 32-lane half of the wave the group is, for G = 32).
+// The work of one splitting edge s for a group of G lanes (G = 16, 32 or 64;
+// lane = 0..G-1; half = which G-lane part of the wave the group is).
 // split_core: the split of edge e = ab (already read and bounds-checked)
 template <int G, int NC>
 __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int e, int2 ab,
@@ -382,6 +382,7 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     // its stored value is overwritten by an exact 0.
     __shared__ uint64_t s_bal[kThreads / 64][kMaxWidth / 32][2];
     static_assert(G == 64 ? NC <= kMaxWidth / 64 : NC <= kMaxWidth / 32, "chunk ballots exceed the LDS slots");
+    static_assert(G != 16 || NC % 2 == 0, "16-lane groups take whole 32-column words");
     const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -407,8 +408,8 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
     // every zero of the edge's sign-vector gives the 2-faces of step 5 (one for
     // a box entry, two for a neuron, in word, bit, sign order), and key r is
     // built by lane r, which here learns the word that holds it.
-    const uint64_t gmask = G == 64 ? ~0ull : 0xFFFFFFFFull;
-    const int gshift = G == 64 ? 0 : 32 * half;
+    const uint64_t gmask = G == 64 ? ~0ull : (1ull << G) - 1ull;
+    const int gshift = G * half;
     uint64_t hsum = 0, rx0 = 0;
     uint64_t kf = 0, kz = 0;  // for key `lane`: the edge's sign word and its zeros there
     int kw = -1, kli = 0;     //                 that word's index, the key's rank inside the word
@@ -429,9 +430,19 @@ __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int
         const int u = w - g.lw0;
         uint64_t cw = 0;
         if (live && u >= 0 && u < nw) {
-            // word u = chunk u / (G/32); inside the chunk's 64-bit ballot, this group's 32 columns
-            const int ku = G == 64 ? (u >> 1) : u, sh = G == 64 ? 32 * (u & 1) : 32 * half;
-            cw = codes_of((uint32_t)(s_bal[wv][ku][0] >> sh), (uint32_t)(s_bal[wv][ku][1] >> sh));
+            if (G == 16) {
+                // word u = chunks 2u and 2u+1: this group's 16 bits of each ballot
+                const int sh = 16 * half;
+                const uint32_t pw = (uint32_t)((s_bal[wv][2 * u][0] >> sh) & 0xFFFFu) |
+                                    ((uint32_t)((s_bal[wv][2 * u + 1][0] >> sh) & 0xFFFFu) << 16);
+                const uint32_t nw2 = (uint32_t)((s_bal[wv][2 * u][1] >> sh) & 0xFFFFu) |
+                                     ((uint32_t)((s_bal[wv][2 * u + 1][1] >> sh) & 0xFFFFu) << 16);
+                cw = codes_of(pw, nw2);
+            } else {
+                // word u = chunk u / (G/32); inside the chunk's 64-bit ballot, this group's 32 columns
+                const int ku = G == 64 ? (u >> 1) : u, sh = G == 64 ? 32 * (u & 1) : 32 * half;
+                cw = codes_of((uint32_t)(s_bal[wv][ku][0] >> sh), (uint32_t)(s_bal[wv][ku][1] >> sh));
+            }
             // an exact zero at a later neuron of the layer: x0 lies on two hyperplanes
             if (~(cw | (cw >> 1)) & vw & gt) bad |= FLAG_ZERO_SIGN;
         }

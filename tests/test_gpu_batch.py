@@ -45,12 +45,16 @@ def test_batch_bit_identical_to_plain(pcx, oracle_lib, monkeypatch):
     bt.close()
 
 
-def test_batch_mixed_dims_output_fallback_and_degenerate(pcx, oracle_lib, monkeypatch):
+@pytest.mark.parametrize("sched", [None, "4", "2"])  # tuned/default; 16 lanes per split; 64 lanes per split
+def test_batch_mixed_dims_output_fallback_and_degenerate(pcx, oracle_lib, monkeypatch, sched):
     monkeypatch.setenv("PCX_NO_TINY", "1")  # the reference is the per-step kernels
+    if sched is not None:
+        monkeypatch.setenv("PCX_BATCH_SCHED", sched)
     nets = [wl.he_mlp([2, 12, 12, 1], 201), wl.he_mlp([3, 10, 10, 1], 202), wl.he_mlp([1, 9, 9, 9, 1], 203),
             wl.he_mlp([3, 64, 64, 64, 1], 5),          # too large for the batched kernel: per-step path
             wl.Net([2, 1, 1], [np.array([[1.0, 1.0]]), np.array([[1.0]])], [np.zeros(1), np.zeros(1)]),  # not generic
-            wl.he_mlp([4, 6, 6, 1], 204), wl.he_mlp([2, 33, 70, 1], 205)]
+            wl.he_mlp([4, 6, 6, 1], 204), wl.he_mlp([2, 33, 70, 1], 205),
+            wl.he_mlp([2, 96, 1], 206), wl.he_mlp([2, 140, 1], 207), wl.he_mlp([3, 20, 12, 1], 208)]
     boxes = [(wl.cube(n.D).lo, wl.cube(n.D).hi) for n in nets]
     mlps = [pcx.MLP.from_net(n) for n in nets]
     bt = pcx.Batch(mlps, boxes, include_output=True)
@@ -127,11 +131,11 @@ def test_batch_schedules_and_tuner(pcx, monkeypatch):
     mlps = [pcx.MLP.from_net(n) for n in nets]
     boxes = [(box.lo, box.hi)] * len(nets)
     ref = None
-    for sc in range(4):
+    for sc in range(6):
         monkeypatch.setenv("PCX_BATCH_SCHED", str(sc))
         bt = pcx.Batch(mlps, boxes)
         st = bt.stats()
-        assert (st.split_lanes, st.select_items) == (64 if sc & 2 else 32, 8 if sc & 1 else 16)
+        assert (st.split_lanes, st.select_items) == (64 if sc & 2 else 16 if sc & 4 else 32, 8 if sc & 1 else 16)
         got = [bt.copy(i) for i in range(len(nets))]
         bt.close()
         if ref is None:
@@ -143,8 +147,8 @@ def test_batch_schedules_and_tuner(pcx, monkeypatch):
     monkeypatch.delenv("PCX_BATCH_SCHED")
     t = pcx.batch_tune(mlps, boxes)
     print(f"tuned: {t}", flush=True)
-    assert t["wg_per_cu"] in (1, 2, 4) and t["split_lanes"] in (32, 64) and t["select_items"] in (8, 16)
-    assert t["candidates"] == 6 and t["ms_best"] <= t["ms_default"]
+    assert t["wg_per_cu"] in (1, 2, 4) and t["split_lanes"] in (16, 32, 64) and t["select_items"] in (8, 16)
+    assert t["candidates"] == 8 and t["ms_best"] <= t["ms_default"]
     bt = pcx.Batch(mlps, boxes)
     st = bt.stats()
     assert (st.wg_per_cu, st.split_lanes, st.select_items) == (t["wg_per_cu"], t["split_lanes"], t["select_items"])
