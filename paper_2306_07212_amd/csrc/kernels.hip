@@ -77,27 +77,28 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Bufs b, int ZS, const double 
 }
 
 // The same evaluation for a narrow layer (N <= kGemvMaxN outputs, e.g. the
-// output neuron): one vertex per thread, its row staged through LDS in chunks
-// of kGemmK (each chunk of the workgroup's rows read in 128-byte row pieces),
+// output neuron): one vertex per thread, 512 rows per workgroup, the rows
+// staged through LDS in chunks of kGemvK (64-byte row pieces: small chunks,
+// 18 KB of LDS per workgroup, keep many workgroups' loads in flight),
 // and the same sequential fma chain over k per output as gemm_tile, so every
 // evaluation kernel rounds alike. Weights are read at uniform addresses. In
 // place as above: a thread reads its whole row before it writes it.
-constexpr int kGemvMaxN = 8;
-__global__ __launch_bounds__(kThreads) void k_gemv(Bufs b, int ZS, const double *in, int in_stride, int relu, int V,
-                                                    int K, int N, const double *__restrict__ Wt,
-                                                    const double *__restrict__ bias, int Wd, int lw0) {
-    __shared__ double hs[kThreads][kGemmK + 1];
+constexpr int kGemvMaxN = 8, kGemvRows = 512, kGemvK = 8;
+__global__ __launch_bounds__(kGemvRows) void k_gemv(Bufs b, int ZS, const double *in, int in_stride, int relu, int V,
+                                                     int K, int N, const double *__restrict__ Wt,
+                                                     const double *__restrict__ bias, int Wd, int lw0) {
+    __shared__ double hs[kGemvRows][kGemvK + 1];
     const int t = threadIdx.x;
-    const int v0 = blockIdx.x * kThreads, v = v0 + t;
+    const int v0 = blockIdx.x * kGemvRows, v = v0 + t;
     double acc[kGemvMaxN];
 #pragma unroll
     for (int n = 0; n < kGemvMaxN; ++n) acc[n] = 0.0;
-    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+    for (int k0 = 0; k0 < K; k0 += kGemvK) {
         __syncthreads();  // the previous chunk has been read
 #pragma unroll
-        for (int i = 0; i < kGemmK; ++i) {
-            // element idx of the chunk: row idx / kGemmK, column idx % kGemmK
-            const int idx = t + kThreads * i, r = idx / kGemmK, k = idx % kGemmK;
+        for (int i = 0; i < kGemvK; ++i) {
+            // element idx of the chunk: row idx / kGemvK, column idx % kGemvK
+            const int idx = t + kGemvRows * i, r = idx / kGemvK, k = idx % kGemvK;
             double h = 0.0;
             if (v0 + r < V && k0 + k < K) {
                 h = in[(size_t)(v0 + r) * in_stride + k0 + k];
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv(Bufs b, int ZS, const double 
             hs[r][k] = h;
         }
         __syncthreads();
-        const int kc = min(kGemmK, K - k0);
+        const int kc = min(kGemvK, K - k0);
         for (int kk = 0; kk < kc; ++kk) {
             const double h = hs[t][kk];
 #pragma unroll
@@ -302,7 +303,7 @@ void launch_gemm(const Bufs &b, int ZS, const double *in, int in_stride, int rel
         return;
     }
     if (N <= kGemvMaxN) {
-        hipLaunchKernelGGL(k_gemv, dim3((V + kThreads - 1) / kThreads), dim3(kThreads), 0, st, b, ZS, in, in_stride,
+        hipLaunchKernelGGL(k_gemv, dim3((V + kGemvRows - 1) / kGemvRows), dim3(kGemvRows), 0, st, b, ZS, in, in_stride,
                            relu, V, K, N, Wt, bias, Wd, lw0);
         return;
     }
@@ -555,8 +556,9 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
     }
 }
 
-// two splits per wave (32-lane groups): the per-split bookkeeping on the sign
-// words runs once for both halves of the wave
+// two splits per wave (32-lane groups; layers of up to 128 neurons take four,
+// in 16-lane groups): the per-split bookkeeping on the sign words runs once
+// for all groups of the wave. (The grid is sized for 32-lane groups.)
 int split_blocks(int S_hint, int Nl) {
     (void)Nl;
     const int groups = kThreads / 32;
@@ -564,26 +566,26 @@ int split_blocks(int S_hint, int Nl) {
     return grid < 1 ? 1 : (grid > 16384 ? 16384 : grid);
 }
 
-template <int NC>
+template <int G, int NC>
 static void launch_split_plain(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_split<32, NC>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+    hipLaunchKernelGGL((k_split<G, NC>), dim3(blocks), dim3(kThreads), 0, st, b, g);
 }
 
 void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     if (!t0 && !t1) {
         // untimed: the plain launch (also what a captured graph records)
-        if (g.Nl <= 32) launch_split_plain<1>(b, g, blocks, st);
-        else if (g.Nl <= 64) launch_split_plain<2>(b, g, blocks, st);
-        else if (g.Nl <= 128) launch_split_plain<4>(b, g, blocks, st);
-        else launch_split_plain<8>(b, g, blocks, st);
+        if (g.Nl <= 32) launch_split_plain<16, 2>(b, g, blocks, st);
+        else if (g.Nl <= 64) launch_split_plain<16, 4>(b, g, blocks, st);
+        else if (g.Nl <= 128) launch_split_plain<16, 8>(b, g, blocks, st);
+        else launch_split_plain<32, 8>(b, g, blocks, st);
         return;
     }
     if (g.Nl <= 32)
-        hipExtLaunchKernelGGL((k_split<32, 1>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
+        hipExtLaunchKernelGGL((k_split<16, 2>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else if (g.Nl <= 64)
-        hipExtLaunchKernelGGL((k_split<32, 2>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
+        hipExtLaunchKernelGGL((k_split<16, 4>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else if (g.Nl <= 128)
-        hipExtLaunchKernelGGL((k_split<32, 4>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
+        hipExtLaunchKernelGGL((k_split<16, 8>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
     else
         hipExtLaunchKernelGGL((k_split<32, 8>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
 }
