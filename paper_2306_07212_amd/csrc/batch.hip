@@ -127,10 +127,23 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // (Not inlined, and given plain pointers rather than the workgroup's Bufs, so
 // that its registers and the Bufs stay out of the split's register allocation.)
+// (The pointers are taken as global memory, so that the loads are global
+// loads whose completion is counted in order, and every operand load is made
+// unconditional, from a clamped in-bounds address, with the value selected
+// after it: the loads of a round are all in flight together.)
+typedef const __attribute__((address_space(1))) double gcdouble;
+typedef const __attribute__((address_space(1))) uint64_t gcuint64;
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) uint64_t guint64;
+
 template <int CT>
-__device__ __noinline__ void eval_mfma(double *Zo, uint64_t *SGo, uint64_t *LWo, int *ctr, int ZS, const double *in,
-                                       int in_stride, int relu, int V, int K, int N, const double *__restrict__ Wt,
-                                       const double *__restrict__ bias, int Wd, int lw0) {
+__device__ __noinline__ void eval_mfma(double *Zo_, uint64_t *SGo_, uint64_t *LWo_, int *ctr, int ZS,
+                                       const double *in_, int in_stride, int relu, int V, int K, int N,
+                                       const double *Wt_, const double *bias_, int Wd, int lw0) {
+    gdouble *Zo = (gdouble *)Zo_;
+    guint64 *SGo = (guint64 *)SGo_, *LWo = (guint64 *)LWo_;
+    gcuint64 *in = (gcuint64 *)in_, *Wt = (gcuint64 *)Wt_;
+    gcdouble *bias = (gcdouble *)bias_;
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = l & 15, q = l >> 4;
     double bv[CT];
@@ -139,34 +152,45 @@ __device__ __noinline__ void eval_mfma(double *Zo, uint64_t *SGo, uint64_t *LWo,
     int zero = 0;
     for (int v0 = wave * 16; v0 < V; v0 += 16 * (kThreads / 64)) {
         const bool arow = v0 + r < V;
-        const double *hp = in + (size_t)(arow ? v0 + r : 0) * in_stride;
+        gcuint64 *hp = in + (size_t)(arow ? v0 + r : 0) * in_stride;
         dbl4 acc[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
-        // one k-step of 4 per MFMA; the next step's operands are loaded before
-        // this step's MFMAs issue
-        double af, bf[CT];
-        auto load = [&](int k0, double &a, double *bw) {
-            const int k = k0 + q;
-            const double h = (arow && k < K) ? hp[k] : 0.0;
-            a = relu ? (h > 0.0 ? h : 0.0) : h;
+        // four k-steps of 4 per round, each with its own operand registers: a
+        // step's operands for the next round are loaded right after its MFMAs
+        // issue, three steps ahead of their use, as raw bits from clamped
+        // in-bounds addresses; the zeros past K (weights) and the ReLU are
+        // applied when the step is used, so no load waits on a condition
+        uint64_t ar[4], br[4][CT];
+        auto load = [&](int k0, uint64_t &a, uint64_t *bw) {
+            const int k = k0 + q, kc = k < K ? k : K - 1;
+            a = hp[kc];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int col = ct * 16 + r;
-                bw[ct] = (k < K && col < N) ? Wt[(size_t)k * N + col] : 0.0;
+                bw[ct] = Wt[(size_t)kc * N + (col < N ? col : N - 1)];
             }
         };
-        load(0, af, bf);
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            double an = 0.0, bn[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) bn[ct] = 0.0;
-            if (k0 + 4 < K) load(k0 + 4, an, bn);
+        for (int st = 0; st < 4; ++st) load(4 * st, ar[st], br[st]);
+        // (every round is whole: a step past K has zero weights, adding +0 to
+        // a sum that is never -0)
+        for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[ct], acc[ct], 0, 0, 0);
-            af = an;
+            for (int st = 0; st < 4; ++st) {
+                const bool kin = k0 + 4 * st + q < K;
+                const double h = __builtin_bit_cast(double, ar[st]);
+                const double af = relu ? (h > 0.0 ? h : 0.0) : h;
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) bf[ct] = bn[ct];
+                for (int ct = 0; ct < CT; ++ct) {
+                    const uint64_t m = (kin && ct * 16 + r < N) ? ~0ull : 0ull;
+                    const double bf = __builtin_bit_cast(double, br[st][ct] & m);
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[ct], 0, 0, 0);
+                }
+                load(k0 + 16 + 4 * st, ar[st], br[st]);
+                // (keeps the loads here, in flight, rather than moved next to their use)
+                asm volatile("" ::: "memory");
+            }
         }
         // bias, store, and the layer's sign words (word p from tiles 2p and 2p+1)
 #pragma unroll
@@ -311,12 +335,37 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
                     gemm_tile(b, ZS, in, ins, l > 0, V, K, N, net.Wt[l], net.b[l], Wd, lw[l], v0, gl->hs, gl->ws);
         }
         __syncthreads();
-        for (int e = t; e < E; e += kThreads) {
-            const int2 ab = b.EDG[e];
-            const uint64_t *ra = b.SG + (size_t)ab.x * Wd, *rb = b.SG + (size_t)ab.y * Wd;
-            int col = kNoCol;
-            for (int w = lw[l]; w < lw[l + 1] && col == kNoCol; ++w) col = first_col(ra[w] ^ rb[w], w, lw[l]);
-            b.NXT[e] = col == kNoCol ? kNone : (uint16_t)col;
+        // each edge's first crossing in the layer: four edges per thread at a
+        // time, their endpoints' first two words of the layer loaded together
+        {
+            const int w0 = lw[l], nw = lw[l + 1] - lw[l];
+            for (int e0 = t; e0 < E; e0 += 4 * kThreads) {
+                int2 ab[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = e0 + i * kThreads;
+                    ab[i] = e < E ? b.EDG[e] : make_int2(0, 0);
+                }
+                uint64_t x0[4], x1[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t *ra = b.SG + (size_t)ab[i].x * Wd + w0, *rb = b.SG + (size_t)ab[i].y * Wd + w0;
+                    x0[i] = ra[0] ^ rb[0];
+                    x1[i] = nw > 1 ? ra[1] ^ rb[1] : 0ull;
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = e0 + i * kThreads;
+                    if (e >= E) continue;
+                    int col = first_col(x0[i], w0, w0);
+                    if (col == kNoCol && nw > 1) col = first_col(x1[i], w0 + 1, w0);
+                    if (col == kNoCol && nw > 2) {
+                        const uint64_t *ra = b.SG + (size_t)ab[i].x * Wd, *rb = b.SG + (size_t)ab[i].y * Wd;
+                        for (int w = w0 + 2; w < w0 + nw && col == kNoCol; ++w) col = first_col(ra[w] ^ rb[w], w, w0);
+                    }
+                    b.NXT[e] = col == kNoCol ? kNone : (uint16_t)col;
+                }
+            }
         }
         if (t == 0) s_misc[0] = __hip_atomic_load(&b.CTR[CTR_FLAGS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
