@@ -59,13 +59,14 @@ struct BatchArgs {
     int verify;        // 1: compare the perturbed sign rows of every pair (pcx_opts.verify_pairs)
 };
 
-// bytes of one workgroup arena: vertex region + edges (14 B) + key slots
+// bytes of one workgroup arena: vertex region + edges (10 B, and a 16-byte
+// split-list entry per possible split: 32 B with alignment) + key slots
 // (partner record 8 B, perturbed entry 4 B) + table (8 B words) + valid words
 // + counters
 inline size_t batch_arena_bytes(size_t vbytes, int ecap, int kcap, uint32_t tcap) {
     size_t k = (size_t)kcap * 12;
     k += 256 - k % 256;
-    return vbytes + (size_t)ecap * 16 + k + (size_t)tcap * sizeof(unsigned long long) + kBatchMaxWords * 8 + 256;
+    return vbytes + (size_t)ecap * 32 + k + (size_t)tcap * sizeof(unsigned long long) + kBatchMaxWords * 8 + 256;
 }
 
 void launch_batch(const BatchArgs &A, int grid, int sched, hipStream_t st);

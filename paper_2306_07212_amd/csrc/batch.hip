@@ -63,10 +63,12 @@ __device__ int block_select(const Bufs &b, int E, uint16_t target, int *s_w) {
             total += ws;
         }
         int pos = run + wave_off + incl - cnt;
+        // each entry carries its edge's endpoints, so a split starts with one load
         while (hit) {
             const int i = __builtin_ctz(hit);
             hit &= hit - 1;
-            b.SPL[pos++] = base + i;
+            const int2 ab = b.EDG[base + i];
+            b.SPLE[pos++] = make_int4(base + i, ab.x, ab.y, 0);
         }
         run += total;
         __syncthreads();
@@ -234,7 +236,14 @@ template <int G, int NC>
 __device__ __forceinline__ void block_split(const Bufs &b, const StepGeom &g, int V0, int E0, int S) {
     constexpr int groups = kThreads / G;
     const int lane = threadIdx.x % G, grp = threadIdx.x / G, half = (threadIdx.x & 63) / G;
-    for (int s = grp; s < S; s += groups) split_one<G, NC>(b, g, V0, E0, s, lane, half, S * g.P);
+    for (int s = grp; s < S; s += groups) {
+        const int4 q = b.SPLE[s];
+        const int2 ab = make_int2(q.y, q.z);
+        if (split_entry_ok(b, q.x, E0) && split_edge_ok(ab, V0))
+            split_core<G, NC>(b, g, V0, E0, s, q.x, ab, lane, half, S * g.P);
+        else if (lane == 0)
+            raise_flag(b.CTR, FLAG_BOUNDS);
+    }
 }
 
 // One network, whole, by the workgroup. Schedule (chosen per size bucket by
@@ -265,8 +274,9 @@ __device__ void run_net(const BatchArgs &A, const BatchNet &net, int ni, Bufs &b
     char *eb = base + A.vbytes;
     b.EDG = (int2 *)eb;
     b.NXT = (uint16_t *)(eb + (size_t)Ecap * 8);
-    b.SPL = (int *)(eb + (size_t)Ecap * 10);
-    char *kb = eb + (size_t)Ecap * 16;
+    b.SPL = nullptr;
+    b.SPLE = (int4 *)(eb + (size_t)Ecap * 16);
+    char *kb = eb + (size_t)Ecap * 32;
     b.PART = (uint64_t *)kb;
     b.PINFO = (uint32_t *)(kb + (size_t)Kcap * 8);
     b.FULL = nullptr;

@@ -117,7 +117,7 @@ struct Bufs {
     uint8_t *NX8;     // [Ecap] the same on the per-step path: 1..255, 0 = none (the layer's first
                       // neuron is never looked up: its splitting edges come from the layer-start scan)
     int *SPL;         // [Scap] split list (batched kernel)
-    int4 *SPLE;       // [Scap] split list of the per-step path: (edge, its two endpoints, 0)
+    int4 *SPLE;       // [Scap] split list: (edge, its two endpoints, 0)
     int *SPLX;        // [Ecap] per-chunk match lists of the compaction (chunk c at its own edge range)
     uint32_t *K32a, *K32b, *VALa, *VALb;  // [Kcap] radix-sort ping-pong
     uint64_t *FULL;   // [Kcap] full 64-bit 2-face hash by slot (sort pairing)
