@@ -44,6 +44,49 @@ std::vector<int> signature(const std::vector<int> &nsteps, const std::vector<int
     return sig;
 }
 
+// This thread's pinned staging buffer of at least `bytes` bytes, kept for its
+// later calls (every caller synchronizes its stream before it returns, so no
+// copy through the old buffer is pending when it grows).
+int staging(size_t bytes, char *&out) {
+    thread_local char *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        const size_t nc = std::max<size_t>(bytes, 64 << 10);
+        if (hipHostMalloc((void **)&buf, nc, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            buf = nullptr;
+            return fail(PCX_ERR_OOM, "pinned staging buffer");
+        }
+        cap = nc;
+    }
+    out = buf;
+    return PCX_OK;
+}
+
+// this thread's pair of timing events on the current device (created once)
+int launch_events(hipEvent_t &a, hipEvent_t &b) {
+    thread_local std::map<int, std::pair<hipEvent_t, hipEvent_t>> ev;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    auto it = ev.find(dev);
+    if (it == ev.end()) {
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
+        hipEvent_t x = nullptr, y = nullptr;
+        HIPCHK(hipEventCreate(&x));
+        HIPCHK(hipEventCreate(&y));
+        it = ev.emplace(dev, std::make_pair(x, y)).first;
+    }
+    a = it->second.first;
+    b = it->second.second;
+    return PCX_OK;
+}
+
+size_t align16(size_t x) { return (x + 15) / 16 * 16; }
+
 }  // namespace
 
 namespace {
@@ -158,6 +201,8 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
     StepRec *rec_dev = nullptr;
     size_t rec_tot = 0;
     std::vector<size_t> rec_off(n, 0);
+    size_t in_bytes = 0, out_bytes = 0, res_bytes = 0;
+    char *in_dev = nullptr, *out_dev = nullptr;
     if (!batched.empty()) {
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
@@ -217,15 +262,26 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
         if ((rc = ar.alloc(&p, capE * sizeof(int2)))) goto fail_out;
         bt->oE = (int2 *)p;
         ar.forget(p);  // owned by the batch from here on
-        if ((rc = ar.alloc(&p, (size_t)n * sizeof(BatchNet)))) goto fail_out;
-        A.nets = (const BatchNet *)p;
-        if ((rc = ar.alloc(&p, batched.size() * sizeof(int)))) goto fail_out;
-        A.order = (const int *)p;
-        if ((rc = ar.alloc(&p, 8 * sizeof(unsigned long long)))) goto fail_out;
-        A.pool = (unsigned long long *)p;
+        // the inputs in one block (the pool counters, zero; the order; the network
+        // descriptors) and the outputs in one block (the results, and the step
+        // log with kStepsNow), each moved by one copy through pinned memory
+        in_bytes = 8 * sizeof(unsigned long long) + align16(batched.size() * sizeof(int)) + (size_t)n * sizeof(BatchNet);
+        if ((rc = ar.alloc(&p, in_bytes))) goto fail_out;
+        in_dev = (char *)p;
+        A.pool = (unsigned long long *)in_dev;
         A.ticket = (int *)(A.pool + 4);
-        if ((rc = ar.alloc(&p, (size_t)n * sizeof(BatchResult)))) goto fail_out;
-        A.res = (BatchResult *)p;
+        A.order = (const int *)(in_dev + 8 * sizeof(unsigned long long));
+        A.nets = (const BatchNet *)(in_dev + 8 * sizeof(unsigned long long) + align16(batched.size() * sizeof(int)));
+        res_bytes = align16((size_t)n * sizeof(BatchResult));
+        {
+            size_t tot = 0;
+            if (keep_steps)
+                for (int i : batched) tot += (size_t)bt->nsteps[i];
+            out_bytes = res_bytes + (steps_mode == kStepsNow ? std::max<size_t>(tot, 1) * sizeof(StepRec) : 0);
+        }
+        if ((rc = ar.alloc(&p, out_bytes))) goto fail_out;
+        out_dev = (char *)p;
+        A.res = (BatchResult *)out_dev;
         if (keep_steps) {
             size_t tot = 0;
             for (int i : batched) tot += (size_t)bt->nsteps[i];
@@ -239,8 +295,7 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
                 }
                 bt->rec_dev = rec_dev;
             } else {
-                if ((rc = ar.alloc(&p, std::max<size_t>(tot, 1) * sizeof(StepRec)))) goto fail_out;
-                rec_dev = (StepRec *)p;
+                rec_dev = (StepRec *)(out_dev + res_bytes);
             }
             size_t off = 0;
             for (int i : batched) {
@@ -271,21 +326,25 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
             A.verify = o.verify_pairs ? 1 : 0;
         }
         {
-            HIPCHK(hipMemcpyAsync((void *)A.nets, nets.data(), (size_t)n * sizeof(BatchNet), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync((void *)A.order, batched.data(), batched.size() * sizeof(int), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemsetAsync(A.pool, 0, 8 * sizeof(unsigned long long), st));
+            char *stg = nullptr;
+            if ((rc = staging(std::max(in_bytes, out_bytes), stg))) goto fail_out;
+            std::memset(stg, 0, 8 * sizeof(unsigned long long));
+            std::memcpy(stg + 8 * sizeof(unsigned long long), batched.data(), batched.size() * sizeof(int));
+            std::memcpy(stg + 8 * sizeof(unsigned long long) + align16(batched.size() * sizeof(int)), nets.data(),
+                        (size_t)n * sizeof(BatchNet));
+            HIPCHK(hipMemcpyAsync(in_dev, stg, in_bytes, hipMemcpyHostToDevice, st));
             hipEvent_t e0, e1;
-            HIPCHK(hipEventCreate(&e0));
-            HIPCHK(hipEventCreate(&e1));
+            if ((rc = launch_events(e0, e1))) goto fail_out;
             HIPCHK(hipEventRecord(e0, st));
             launch_batch(A, grid, sched, st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipMemcpyAsync(bt->res.data(), A.res, (size_t)n * sizeof(BatchResult), hipMemcpyDeviceToHost, st));
-            std::vector<StepRec> rec(steps_mode == kStepsNow ? rec_tot : 0);
-            if (!rec.empty())
-                HIPCHK(hipMemcpyAsync(rec.data(), rec_dev, rec_tot * sizeof(StepRec), hipMemcpyDeviceToHost, st));
+            // (stream order: the input copy out of the staging buffer is done before this one lands there)
+            HIPCHK(hipMemcpyAsync(stg, out_dev, out_bytes, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
+            std::memcpy(bt->res.data(), stg, (size_t)n * sizeof(BatchResult));
+            std::vector<StepRec> rec(steps_mode == kStepsNow ? rec_tot : 0);
+            if (!rec.empty()) std::memcpy(rec.data(), stg + res_bytes, rec_tot * sizeof(StepRec));
             for (int i : batched) {
                 if (steps_mode != kStepsNow || bt->res[i].status != BATCH_OK) continue;
                 auto &sv = bt->steps[i];
@@ -299,8 +358,6 @@ int batch_run(int32_t n, const pcx_mlp *const *mlps, const double *lo, const dou
                 }
             }
             HIPCHK(hipEventElapsedTime(&kms, e0, e1));
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
         }
         bt->workgroups = grid;
         bt->wg_per_cu = wpc;
