@@ -46,7 +46,9 @@ std::vector<int> signature(const std::vector<int> &nsteps, const std::vector<int
 
 // This thread's pinned staging buffer of at least `bytes` bytes, kept for its
 // later calls (every caller synchronizes its stream before it returns, so no
-// copy through the old buffer is pending when it grows).
+// copy through the old buffer is pending when it grows). Like the thread's
+// other pinned buffers and events it is never released: the runtime may be
+// gone at thread exit.
 int staging(size_t bytes, char *&out) {
     thread_local char *buf = nullptr;
     thread_local size_t cap = 0;
