@@ -344,6 +344,12 @@ template <int G, int NC>
 __device__ __forceinline__ void split_core(const Bufs &b, const StepGeom &g, int V0, int E0, int s, int e, int2 ab,
                                            int lane, int half, int nslots) {
     const int D = g.D, Wd = g.Wd, ZS = g.ZS;
+    // every 2-face key of the split is built by a lane of the group (callers
+    // choose G >= 2(D - 1)); anything else is refused as an internal error
+    if (g.P > G) {
+        if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
+        return;
+    }
     // the per-column predicates below (c < N, c vs j, c >= zlo) are cheap to
     // recompute; an empty asm makes their bounds opaque per split so that they
     // are not hoisted out of the caller's loop into dozens of live lane masks

@@ -566,28 +566,33 @@ int split_blocks(int S_hint, int Nl) {
     return grid < 1 ? 1 : (grid > 16384 ? 16384 : grid);
 }
 
+// untimed: the plain launch (also what a captured graph records); timed: the
+// launch records its own start and end events
 template <int G, int NC>
-static void launch_split_plain(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_split<G, NC>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+static void launch_split_as(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0,
+                            hipEvent_t t1) {
+    if (!t0 && !t1)
+        hipLaunchKernelGGL((k_split<G, NC>), dim3(blocks), dim3(kThreads), 0, st, b, g);
+    else
+        hipExtLaunchKernelGGL((k_split<G, NC>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
 }
 
 void launch_split(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
-    if (!t0 && !t1) {
-        // untimed: the plain launch (also what a captured graph records)
-        if (g.Nl <= 32) launch_split_plain<16, 2>(b, g, blocks, st);
-        else if (g.Nl <= 64) launch_split_plain<16, 4>(b, g, blocks, st);
-        else if (g.Nl <= 128) launch_split_plain<16, 8>(b, g, blocks, st);
-        else launch_split_plain<32, 8>(b, g, blocks, st);
-        return;
+    // a group builds each of a split's 2-face keys in a lane of its own: 16-lane
+    // groups only while 2(D - 1) <= 16
+    const bool narrow = g.P <= 16;
+    if (g.Nl <= 32) {
+        if (narrow) launch_split_as<16, 2>(b, g, blocks, st, t0, t1);
+        else launch_split_as<32, 1>(b, g, blocks, st, t0, t1);
+    } else if (g.Nl <= 64) {
+        if (narrow) launch_split_as<16, 4>(b, g, blocks, st, t0, t1);
+        else launch_split_as<32, 2>(b, g, blocks, st, t0, t1);
+    } else if (g.Nl <= 128) {
+        if (narrow) launch_split_as<16, 8>(b, g, blocks, st, t0, t1);
+        else launch_split_as<32, 4>(b, g, blocks, st, t0, t1);
+    } else {
+        launch_split_as<32, 8>(b, g, blocks, st, t0, t1);
     }
-    if (g.Nl <= 32)
-        hipExtLaunchKernelGGL((k_split<16, 2>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
-    else if (g.Nl <= 64)
-        hipExtLaunchKernelGGL((k_split<16, 4>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
-    else if (g.Nl <= 128)
-        hipExtLaunchKernelGGL((k_split<16, 8>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
-    else
-        hipExtLaunchKernelGGL((k_split<32, 8>), dim3(blocks), dim3(kThreads), 0, st, t0, t1, 0, b, g);
 }
 
 // ---------------------------------------------------- step 5b: radix sort

@@ -65,6 +65,7 @@ def test_plain_small_matches_oracle_and_golden(oracle_lib, pcx):
     ([2, 70, 1], 107, False),        # layer spanning three sign words
     ([3, 64, 1], 108, True),
     ([2, 1, 1, 1], 109, False),       # width-1 layers
+    ([10, 9, 2, 1], 111, False),      # D = 10: splits with 18 key slots (more than a 16-lane group)
 ])
 @pytest.mark.parametrize("pairing", ["hash", "sort"])
 @pytest.mark.parametrize("path", ["default", "per-step"])
