@@ -122,9 +122,10 @@ __device__ int block_pair(const Bufs &b, const StepGeom &g, int V0, int E1, int 
 // row l/16 + 4i, column l%16), its inputs and the weights read straight from
 // memory (no LDS, no barrier: a wave reads every input of its rows before it
 // writes them, so the evaluation can be in place). A chain of these MFMAs
-// rounds as the sequential FMA chain over k from zero does (the zero padding
-// of k adds +0 to a sum that is never -0), and then + bias: the values are
-// those of every other evaluation kernel, bit for bit.
+// rounds as the sequential FMA chain over k from zero does (the padding of k
+// adds a zero, which leaves any sum other than -0 unchanged, and a sum started
+// at +0 becomes -0 only if a product underflows), and then + bias: the values
+// are those of every other evaluation kernel, bit for bit.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // (Not inlined, and given plain pointers rather than the workgroup's Bufs, so
@@ -175,8 +176,8 @@ __device__ __noinline__ void eval_mfma(double *Zo_, uint64_t *SGo_, uint64_t *LW
         };
 #pragma unroll
         for (int st = 0; st < 4; ++st) load(4 * st, ar[st], br[st]);
-        // (every round is whole: a step past K has zero weights, adding +0 to
-        // a sum that is never -0)
+        // (every round is whole: a step past K has zero weights, adding a zero
+        // to the sum)
         for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
