@@ -66,6 +66,7 @@ def test_plain_small_matches_oracle_and_golden(oracle_lib, pcx):
     ([3, 64, 1], 108, True),
     ([2, 1, 1, 1], 109, False),       # width-1 layers
     ([10, 9, 2, 1], 111, False),      # D = 10: splits with 18 key slots (more than a 16-lane group)
+    ([3, 100, 1], 112, True),         # a layer of 65-128 neurons: 16-lane splits, 8 columns per lane
 ])
 @pytest.mark.parametrize("pairing", ["hash", "sort"])
 @pytest.mark.parametrize("path", ["default", "per-step"])
