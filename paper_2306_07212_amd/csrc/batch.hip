@@ -241,7 +241,7 @@ __device__ __forceinline__ void block_split(const Bufs &b, const StepGeom &g, in
         const int4 q = b.SPLE[s];
         const int2 ab = make_int2(q.y, q.z);
         if (split_entry_ok(b, q.x, E0) && split_edge_ok(ab, V0))
-            split_core<G, NC>(b, g, V0, E0, s, q.x, ab, lane, half, S * g.P);
+            split_core<G, NC, false>(b, g, V0, E0, s, q.x, ab, lane, half, S * g.P);
         else if (lane == 0)
             raise_flag(b.CTR, FLAG_BOUNDS);
     }

@@ -542,6 +542,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
         g.sbits = slot_bits(nslots);
     }
     constexpr int groups = kThreads / G;
+    // new vertices' rows streamed past the caches for layers wider than 128 neurons
+    constexpr bool kStream = G * NC > 128;
     const int lane = threadIdx.x % G;
     const int grp = threadIdx.x / G;
     const int half = (threadIdx.x & 63) / G;
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
             if (lane == 0) raise_flag(b.CTR, FLAG_BOUNDS);
             continue;
         }
-        split_core<G, NC>(b, g, V0, E0, s, q.x, ab, lane, half, nslots);
+        split_core<G, NC, kStream>(b, g, V0, E0, s, q.x, ab, lane, half, nslots);
     }
 }
 
