@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "device.h"
 #include "internal.h"
@@ -560,7 +561,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_split(Bufs b, StepGeom g) {
 
 // two splits per wave (32-lane groups; layers of up to 128 neurons take four,
 // in 16-lane groups): the per-split bookkeeping on the sign words runs once
-// for all groups of the wave. (The grid is sized for 32-lane groups.)
+// for all groups of the wave. (The grid is sized for 32-lane groups; the
+// launch cuts it to one residency wave, split_resident below.)
 int split_blocks(int S_hint, int Nl) {
     (void)Nl;
     const int groups = kThreads / 32;
@@ -568,11 +570,37 @@ int split_blocks(int S_hint, int Nl) {
     return grid < 1 ? 1 : (grid > 16384 ? 16384 : grid);
 }
 
+// Workgroups of k_split<G, NC> that the device holds at once (one residency
+// wave), per device, from the occupancy of the compiled kernel; 0 if unknown.
+// A split grid is cut to one such wave and the grid-stride loop takes the
+// rest: on the 768-neuron network (five workgroups per CU, 1280 in all) one
+// wave took 57.1-57.8 us per split launch, 0.8 wave 60.2-60.6, 1.2 waves 65-66,
+// two waves 57.6, and one workgroup per eight splits (up to ~12.5K) 59.0-59.7.
+template <int G, int NC>
+static int split_resident() {
+    constexpr int kDevs = 64;
+    static std::atomic<int> cache[kDevs];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return 0;
+    int r = cache[dev].load(std::memory_order_relaxed);
+    if (r) return r;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split<G, NC>, kThreads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+        cus < 1)
+        return 0;
+    r = per_cu * cus;
+    cache[dev].store(r, std::memory_order_relaxed);
+    return r;
+}
+
 // untimed: the plain launch (also what a captured graph records); timed: the
 // launch records its own start and end events
 template <int G, int NC>
 static void launch_split_as(const Bufs &b, const StepGeom &g, int blocks, hipStream_t st, hipEvent_t t0,
                             hipEvent_t t1) {
+    const int wave = split_resident<G, NC>();
+    if (wave > 0 && blocks > wave) blocks = wave;
     if (!t0 && !t1)
         hipLaunchKernelGGL((k_split<G, NC>), dim3(blocks), dim3(kThreads), 0, st, b, g);
     else
