@@ -97,12 +97,18 @@ __device__ __forceinline__ uint32_t eq_bytes4(uint32_t v, uint32_t t4) {
     return ((z >> 7) * 0x00204081u) >> 21 & 0xFu;  // gather the four top bits
 }
 
-// bit i: edge base + i has first crossing `target` (kScanItems one-byte entries)
-__device__ __forceinline__ uint32_t match32b(const uint8_t *__restrict__ nx, int base, int E, uint8_t target) {
+__device__ __forceinline__ void load32b(const uint8_t *__restrict__ nx, int base, uint4 &a, uint4 &c) {
+    a = *reinterpret_cast<const uint4 *>(nx + base);
+    c = *reinterpret_cast<const uint4 *>(nx + base + 16);
+}
+
+// bit i: edge base + i has first crossing `target` (kScanItems one-byte
+// entries): from the words load32b fetched for a whole group, else (the
+// chunk's last, partial group) from the bytes one by one
+__device__ __forceinline__ uint32_t match32b_raw(const uint8_t *__restrict__ nx, int base, int E, uint8_t target,
+                                                 uint4 a, uint4 c) {
     uint32_t hit = 0;
     if (base + kScanItems <= E) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(nx + base);
-        const uint4 c = *reinterpret_cast<const uint4 *>(nx + base + 16);
         const uint32_t w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
         const uint32_t t4 = 0x01010101u * target;
 #pragma unroll

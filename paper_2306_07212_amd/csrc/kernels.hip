@@ -338,9 +338,16 @@ __global__ __launch_bounds__(kThreads) void k_sel_local(Bufs b, uint16_t target,
     int c0, c1;
     sel_chunk(E, c0, c1);
     int run = c0;
+    // the next tile's bytes are loaded before this tile's scan, so that their
+    // latency hides behind it (raw words carried, compared at the next round)
+    int nbase = c0 + t * kScanItems;
+    uint4 ra = make_uint4(0, 0, 0, 0), rc = ra;
+    if (nbase + kScanItems <= c1) load32b(b.NX8, nbase, ra, rc);
     for (int tb = c0; tb < c1; tb += kScanTile) {
-        const int base = tb + t * kScanItems;
-        uint32_t hit = base < c1 ? match32b(b.NX8, base, c1, (uint8_t)target) : 0u;
+        const int base = nbase;
+        uint32_t hit = base < c1 ? match32b_raw(b.NX8, base, c1, (uint8_t)target, ra, rc) : 0u;
+        nbase = base + kScanTile;
+        if (nbase + kScanItems <= c1) load32b(b.NX8, nbase, ra, rc);
         const int cnt = __popc(hit);
         int incl = cnt;
 #pragma unroll
@@ -377,6 +384,14 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par, int st
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int c0, c1;
     sel_chunk(E, c0, c1);
+    // the first round of entries is loaded while the chunk's offset is summed
+    const int n = b.SELCNT[blockIdx.x];
+    int e0 = 0;
+    int2 ab0 = make_int2(0, 0);
+    if (t < n) {
+        e0 = b.SPLX[c0 + t];
+        ab0 = b.EDG[e0];
+    }
     int pre = 0;
     for (int i = t; i < (int)blockIdx.x; i += kThreads) pre += b.SELCNT[i];
     for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
@@ -391,8 +406,9 @@ __global__ __launch_bounds__(kThreads) void k_sel_gather(Bufs b, int par, int st
     __syncthreads();
     // each entry carries its edge's endpoints, so the split starts from them
     // without another dependent load
-    const int n = b.SELCNT[blockIdx.x], base = s_base;
-    for (int i = t; i < n; i += kThreads) {
+    const int base = s_base;
+    if (t < n) b.SPLE[base + t] = make_int4(e0, ab0.x, ab0.y, 0);
+    for (int i = t + kThreads; i < n; i += kThreads) {
         const int e = b.SPLX[c0 + i];
         const int2 ab = b.EDG[e];
         b.SPLE[base + i] = make_int4(e, ab.x, ab.y, 0);
