@@ -597,14 +597,22 @@ static int split_resident() {
     constexpr int kDevs = 64;
     static std::atomic<int> cache[kDevs];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (dev < 0 || dev >= kDevs) return 0;
     int r = cache[dev].load(std::memory_order_relaxed);
     if (r) return r;
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split<G, NC>, kThreads, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
-        cus < 1)
+        cus < 1) {
+        // (the launch then keeps its grid; the error must not be reported by
+        // the caller's check of the launch)
+        (void)hipGetLastError();
         return 0;
+    }
     r = per_cu * cus;
     cache[dev].store(r, std::memory_order_relaxed);
     return r;
